@@ -1,0 +1,225 @@
+/*
+ * mu3e.h -- C ABI of the MI355X (gfx950) online event selection for Mu3e.
+ *
+ * Method: V. Henkys, B. Schmidt, N. Berger, "Online Event Selection for
+ * Mu3e using GPUs" (arXiv 2206.11535):
+ *   Section IV-A  Selection Cuts (eq. sel-cut-delta-lambda, eq. sel-cut-phi,
+ *                 eq. rt-cut; Alg. 2)
+ *   Section IV-B  Track Reconstruction (eq. objective-function, triplet fit
+ *                 linearised around the transverse circle, weighted mean
+ *                 curvature, eq. objective-function-global, chi2 < 32; Alg. 3)
+ *   Section IV-C  Vertex Fit (circle intersections, weighted 2D vertex,
+ *                 eq. track-error, z back-projection, vertex chi2, signal
+ *                 tests; Alg. 4)
+ *   Section V     frame flow (Alg. 1), "marked for storage" on overflow.
+ *
+ * Conventions.  Units mm, MeV, tesla, radian.  Field along +z; positive
+ * charges turn clockwise seen from +z and have positive signed circumradius
+ * and curvature.  Hits are float32 structure-of-arrays, sorted by frame and
+ * then layer; frame f, layer l owns hits [layer_offsets[4f+l],
+ * layer_offsets[4f+l+1]).  Indices and counts are int32, flags uint32.
+ *
+ * Memory.  Unless stated otherwise every pointer is a DEVICE pointer and
+ * every buffer is owned by the caller; the library never allocates on these
+ * paths.  Scratch memory is a caller-provided workspace whose size is
+ * queried first.  Every call is asynchronous on the given HIP stream
+ * (NULL = default stream) and re-entrant for distinct workspaces.
+ *
+ * Errors.  Argument errors are reported synchronously as a negative status
+ * and nothing is launched.  Conditions only known on the device (a candidate
+ * list in the workspace filled up) are reported in the workspace's status
+ * word, readable after the stream has been synchronised (mu3e_debug_t).
+ * Exceeding a *method* cap (max_triplets, max_tracks, max_combos,
+ * max_layer_hits) is not an error: the frame's overflow flag is set and the
+ * frame is kept, as the paper's implementation marks such frames for storage.
+ */
+#ifndef MU3E_H
+#define MU3E_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MU3E_OK = 0,
+  MU3E_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad parameter */
+  MU3E_ERR_HIP = -2,           /* a HIP runtime call failed                   */
+  MU3E_ERR_CAPACITY = -3,      /* workspace too small for the request         */
+  MU3E_ERR_UNSUPPORTED = -4    /* parameter beyond what the kernels support   */
+} mu3e_status;
+
+/* Per-frame flag bits (frame_flags). */
+enum {
+  MU3E_KEEP = 1u,          /* frame is kept (any other bit set)                */
+  MU3E_TRIPLET_OVF = 2u,   /* more than max_triplets triplets passed the cuts  */
+  MU3E_TRACK_OVF = 4u,     /* more than max_tracks tracks passed chi2 < max    */
+  MU3E_COMBO_OVF = 8u,     /* more than max_combos e+e+e- triples passed dE    */
+  MU3E_VERTEX = 16u,       /* a signal-like vertex was found                   */
+  MU3E_HITS_OVF = 32u      /* a layer holds more than max_layer_hits hits      */
+};
+
+/* Largest per-layer hit count the kernels stage in LDS. */
+#define MU3E_MAX_LAYER_HITS 128
+
+/* Hits of a batch of frames (device pointers).  layer and sensor may be NULL
+ * for calls that do not need them. */
+typedef struct {
+  const float *x, *y, *z;            /* [n_hits] mm                              */
+  const uint16_t *layer, *sensor;    /* [n_hits]                                 */
+  const int32_t *layer_offsets;      /* [4*n_frames+1], non-decreasing, [0] = 0  */
+  int32_t n_frames, n_hits;
+} mu3e_hits_t;
+
+typedef struct { float lo, hi; } mu3e_window_t;   /* pass iff lo <= q <= hi */
+
+/* Selection parameters (host struct, passed by pointer, copied at launch). */
+typedef struct {
+  float r_layer[4];          /* nominal layer radii (25, 31, 73, 85)              */
+  float z_half[4];           /* layer half lengths                                */
+  float b_tesla;             /* solenoid field                                    */
+  float x_over_x0;           /* radiation length fraction per layer               */
+  float sigma_pixel;         /* pixel resolution (pitch / sqrt 12)                */
+  mu3e_window_t dlambda;     /* tan(lambda_12) - tan(lambda_01)                   */
+  mu3e_window_t cosphi01;    /* cos of the azimuth between layer-0/1 hits         */
+  mu3e_window_t cosphi12;    /* cos of the azimuth between layer-1/2 hits         */
+  mu3e_window_t rtc_abs;     /* |signed transverse circumradius|                  */
+  float chi2_track_max;      /* keep tracks with chi2_global < this (32)          */
+  int32_t max_triplets;      /* cap of the selected-triplet list (768)            */
+  int32_t max_tracks;        /* cap of the track list                             */
+  int32_t max_combos;        /* cap of the energy-passing e+e+e- triple list      */
+  int32_t max_layer_hits;    /* <= MU3E_MAX_LAYER_HITS                            */
+  float de_max;              /* |sum E - m_mu| <= de_max                          */
+  float r_target;            /* target radius (19)                                */
+  float target_tol;          /* intersections within r_target + target_tol        */
+  float chi2_vertex_max;     /* vertex chi2 <= this                               */
+  float d_target_max;        /* distance of the vertex to the target surface      */
+  float p_sum_max;           /* |vector sum of the three momenta|                 */
+} mu3e_params_t;
+
+/* Optional debug view, filled on return of mu3e_select_frames (host struct
+ * holding device pointers into the caller's workspace).  After the stream is
+ * synchronised:
+ *   counters[0]  triplets appended to the triplet list (true count, may
+ *                exceed triplet_capacity)
+ *   counters[1]  tracks appended to the track list (true count)
+ *   counters[2]  status bits: 1 triplet list full, 2 track list full,
+ *                4 a frame's layer_offsets were malformed (decreasing,
+ *                negative or beyond n_hits; that frame was skipped)
+ *   triplets     [triplet_capacity][2]: frame, packed frame-local indices
+ *                i0 | i1 << 8 | i2 << 16 (hit = layer_offsets[4f+l] + il)
+ *   tracks       [track_capacity][8]: frame, hit0, hit1, hit2, hit3, next,
+ *                float bits of kappa_bar, float bits of chi2_global
+ * Triplets of frames flagged MU3E_TRIPLET_OVF may appear in the list; they
+ * are never fitted. */
+typedef struct {
+  const int32_t *counters;
+  const int32_t *triplets;
+  const int32_t *tracks;
+  int32_t triplet_capacity, track_capacity;
+} mu3e_debug_t;
+
+const char *mu3e_status_string(mu3e_status s);
+
+/* Workspace bytes for mu3e_select_frames over n_frames frames with room for
+ * triplet_capacity selected triplets and track_capacity tracks in total.  A
+ * run whose lists fill up reports it in counters[2] (mu3e_debug_t); its
+ * outputs are then incomplete and the call should be repeated with the
+ * true counts from counters[0..1].  Returns 0 for invalid sizes. */
+size_t mu3e_select_workspace_size(int32_t n_frames, int32_t triplet_capacity,
+                                  int32_t track_capacity);
+
+/* The whole selection (Sections IV-A..IV-C, Alg. 1) for every frame:
+ *   frame_flags  [n_frames]     MU3E_* bits
+ *   frame_counts [3*n_frames]   triplets passing the cuts, tracks passing the
+ *                               chi2 cut, e+e+e- triples passing the energy
+ *                               test (exact counts; a stage skipped after an
+ *                               overflow reports 0)
+ *   frame_vertex [4*n_frames]   x, y, z, chi2 of the minimum-chi2 passing
+ *                               vertex, NaN if none
+ * dbg may be NULL.  Layer and sensor arrays are not read. */
+mu3e_status mu3e_select_frames(const mu3e_hits_t *hits, const mu3e_params_t *params,
+                               uint32_t *frame_flags, int32_t *frame_counts,
+                               float *frame_vertex, void *workspace, size_t workspace_bytes,
+                               int32_t triplet_capacity, int32_t track_capacity,
+                               mu3e_debug_t *dbg, hipStream_t stream);
+
+/* mu3e_select_frames that also records stage_events[0..4] on the stream:
+ * before the first kernel, then after the cuts (Alg. 2), track (Alg. 3),
+ * vertex-preparation and vertex (Alg. 4) kernels, for per-stage timing with
+ * hipEventElapsedTime.  The events are created and owned by the caller;
+ * stage_events may be NULL. */
+mu3e_status mu3e_select_frames_timed(const mu3e_hits_t *hits, const mu3e_params_t *params,
+                                     uint32_t *frame_flags, int32_t *frame_counts,
+                                     float *frame_vertex, void *workspace, size_t workspace_bytes,
+                                     int32_t triplet_capacity, int32_t track_capacity,
+                                     mu3e_debug_t *dbg, hipStream_t stream,
+                                     hipEvent_t *stage_events);
+
+/* Single triplet fit (Section IV-B) of n explicit triplets of global hit
+ * indices trip[n][3] (layer order 0,1,2 or 1,2,3).  out[n][8]: kappa,
+ * sigma^2_kappa, chi2_min, R*, sigma^2_R, signed circumradius, theta_C1,
+ * theta_C2.  A degenerate triplet (collinear in the transverse plane) or one
+ * with a hit index outside [0, n_hits) gives NaN in all eight fields. */
+mu3e_status mu3e_fit_triplets(const mu3e_hits_t *hits, const int32_t *trip, int32_t n,
+                              const mu3e_params_t *params, float *out, hipStream_t stream);
+
+/* Tracks grouped by frame: frame f owns tracks [frame_offsets[f],
+ * frame_offsets[f+1]) of hit[n_tracks][4] (global hit indices, layers 0..3). */
+typedef struct {
+  const int32_t *hit;
+  const int32_t *frame_offsets;      /* [n_frames+1] */
+  int32_t n_frames, n_tracks;
+} mu3e_tracks_t;
+
+/* Workspace bytes of mu3e_vertex for n_tracks tracks (0 if n_tracks < 0). */
+size_t mu3e_vertex_workspace_size(int32_t n_tracks);
+
+/* Vertex stage (Section IV-C, Alg. 4) on given tracks: the track parameters
+ * are recomputed from the hits in float64, e+e+e- triples pass the energy
+ * test, the vertex estimate and the three signal tests decide MU3E_VERTEX.
+ *   frame_flags  [n_frames]   MU3E_TRACK_OVF | MU3E_COMBO_OVF | MU3E_VERTEX |
+ *                             MU3E_KEEP (overwritten)
+ *   frame_combos [n_frames]   energy-passing triples
+ *   frame_vertex [4*n_frames] as in mu3e_select_frames
+ * Tracks with a hit index outside [0, n_hits) are ignored; a frame whose
+ * range is malformed (decreasing or beyond n_tracks) forms no triple. */
+mu3e_status mu3e_vertex(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
+                        const mu3e_params_t *params, uint32_t *frame_flags,
+                        int32_t *frame_combos, float *frame_vertex, void *workspace,
+                        size_t workspace_bytes, hipStream_t stream);
+
+/* ---- Alignment (differentiable form) ---------------------------------
+ * theta[n_sensors][4] = (tx, ty, tz, alpha) per sensor: a hit h on sensor s
+ * (hits->sensor, required here) is moved to R_z(alpha_s) h + (tx, ty, tz)_s
+ * before the triplet fit of Section IV-B.  trip[n][3] are global hit indices
+ * of triplets on consecutive layers (a frozen set, e.g. both triplets of
+ * every accepted track); n_sensors <= 2048. */
+
+/* chi2[n]: the triplet-fit chi2 of each triplet after alignment (float32
+ * fit); NaN for a degenerate triplet or an index out of range. */
+mu3e_status mu3e_align_chi2(const mu3e_hits_t *hits, const int32_t *trip, int32_t n,
+                            const float *theta, int32_t n_sensors, const mu3e_params_t *params,
+                            float *chi2, hipStream_t stream);
+
+/* Workspace bytes of mu3e_align_backward (0 if n_sensors is out of range). */
+size_t mu3e_align_workspace_size(int32_t n_sensors);
+
+/* Hand-written adjoint: grad_theta[n_sensors][4] (overwritten) =
+ * sum_t grad_chi2[t] * d chi2_t / d theta, through the circumcircle, the
+ * linearised fit and the Highland width; the discrete choices of the fit
+ * stay fixed.  Accumulation in float64. */
+mu3e_status mu3e_align_backward(const mu3e_hits_t *hits, const int32_t *trip, int32_t n,
+                                const float *theta, int32_t n_sensors,
+                                const mu3e_params_t *params, const float *grad_chi2,
+                                float *grad_theta, void *workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MU3E_H */

@@ -783,10 +783,11 @@ void oc_vertex4(const double* h, int n, const double* params, double* out) {
 // triplets, with A_s(h) = R_z(alpha_s) h + (tx, ty, tz)_s per sensor s, and
 // its exact gradient by forward-mode dual numbers (12 directions per
 // triplet: the four parameters of each of its three hits' sensors).
-// theta [S][4], grad [S][4] (accumulated).  Returns L.
+// theta [S][4], grad [S][4] (accumulated); weight [n] optional (NULL = 1):
+// L = sum_t weight_t chi2_t.  Returns L.
 double oc_align_loss_grad(const float* x, const float* y, const float* z, const uint16_t* sensor,
                           const int32_t* trip /*[n][3]*/, int n, const double* theta, int n_sensors,
-                          const double* params, double* grad, int with_grad) {
+                          const double* params, double* grad, int with_grad, const double* weight) {
   Params P = unpack(params);
   double L = 0;
   std::vector<double> G(with_grad ? (size_t)n_sensors * 4 : 0, 0.0);
@@ -815,10 +816,11 @@ double oc_align_loss_grad(const float* x, const float* y, const float* z, const 
         }
         Fit<Dual<12>> f;
         if (!triplet_fit(h[0], h[1], h[2], P, f)) continue;
-        l += f.chi2.v;
+        const double w = weight ? weight[i] : 1.0;
+        l += w * f.chi2.v;
         for (int k = 0; k < 3; ++k) {
           int s = sensor[trip[3 * i + k]];
-          for (int j = 0; j < 4; ++j) g[4 * s + j] += f.chi2.d[4 * k + j];
+          for (int j = 0; j < 4; ++j) g[4 * s + j] += w * f.chi2.d[4 * k + j];
         }
       } else {
         double h[3][3];
@@ -832,7 +834,7 @@ double oc_align_loss_grad(const float* x, const float* y, const float* z, const 
         }
         Fit<double> f;
         if (!triplet_fit(h[0], h[1], h[2], P, f)) continue;
-        l += f.chi2;
+        l += (weight ? weight[i] : 1.0) * f.chi2;
       }
     }
 #pragma omp critical

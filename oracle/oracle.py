@@ -69,7 +69,7 @@ def lib():
         L.oc_track4.argtypes = [P, I, P, P, P]
         L.oc_vertex4.argtypes = [P, I, P, P]
         L.oc_align_loss_grad.restype = D
-        L.oc_align_loss_grad.argtypes = [P, P, P, P, P, I, P, I, P, P, I]
+        L.oc_align_loss_grad.argtypes = [P, P, P, P, P, I, P, I, P, P, I, P]
         L.oc_param_count.restype = I
         _lib = L
     return _lib
@@ -200,9 +200,9 @@ def vertex4(h: np.ndarray, params: dict):
     return out
 
 
-def align_loss_grad(fs, trip: np.ndarray, theta: np.ndarray, params: dict, grad: bool = True):
-    """L(theta) = sum over triplets of the fit chi2 after per-sensor alignment,
-    and dL/dtheta [S, 4] (exact, forward-mode duals)."""
+def align_loss_grad(fs, trip: np.ndarray, theta: np.ndarray, params: dict, grad: bool = True, weight=None):
+    """L(theta) = sum over triplets of (weight *) the fit chi2 after per-sensor
+    alignment, and dL/dtheta [S, 4] (exact, forward-mode duals)."""
     x = np.ascontiguousarray(fs.x, np.float32)
     y = np.ascontiguousarray(fs.y, np.float32)
     z = np.ascontiguousarray(fs.z, np.float32)
@@ -211,6 +211,7 @@ def align_loss_grad(fs, trip: np.ndarray, theta: np.ndarray, params: dict, grad:
     th = np.ascontiguousarray(theta, np.float64)
     S = th.shape[0]
     g = np.zeros((S, 4))
+    w = None if weight is None else np.ascontiguousarray(weight, np.float64)
     Lv = lib().oc_align_loss_grad(_ptr(x), _ptr(y), _ptr(z), _ptr(s), _ptr(t), len(t), _ptr(th), S,
-                                  _ptr(pack_params(params)), _ptr(g), int(grad))
+                                  _ptr(pack_params(params)), _ptr(g), int(grad), None if w is None else _ptr(w))
     return Lv, g

@@ -1,0 +1,1055 @@
+// HIP kernels (gfx950) and C ABI of the online event selection.
+//
+// Plain form of the selection, three stages per batch of frames:
+//   k_cuts     one wave64 per frame, frames dealt cyclically to a static grid
+//              (Section V-B, Alg. 1 and Alg. 2): the frame's layer-0..2 hits
+//              are staged in LDS; per layer-1 hit a 128-bit mask of layer-0
+//              partners passing the Phi01 window is built; (h1, h2) pairs
+//              passing Phi12 are streamed through an LDS queue and each full
+//              wave of pairs joins against its Phi01 partners (Delta lambda,
+//              then r_tc); survivors are compacted with ballot/popcount into an
+//              LDS buffer and appended to a global triplet list.
+//   k_tracks   one thread per selected triplet over the flat list (Alg. 3):
+//              fit, layer-3 extension, second fit, weighted curvature,
+//              chi2 < 32; tracks are pushed onto a per-frame list.
+//   k_vcand    per frame: track cap, frames able to form an e+e+e- triple
+//   k_vprep    per track of such frames: float64 refit
+//   k_vframes  one wave per candidate frame: energy test over the triples,
+//              combination cap, vertex estimate and signal tests (Alg. 4).
+//
+// Decisions taken on float32 values are certain with respect to the exact
+// value unless the value lies within a bound of its own rounding error around
+// the edge; then the candidate is re-evaluated in float64.
+
+#include "mu3e.h"
+#include "mu3e_math.hpp"
+#include "mu3e_adjoint.hpp"
+
+#include <math.h>
+#include <string.h>
+
+using namespace mu3e;
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kTripBuf = 1024;               // LDS triplet buffer per frame
+constexpr int kStreamAbove = kTripBuf - 64;  // larger caps: stream survivors out
+constexpr int kCounters = 64;                // int32 counters at the workspace head
+
+// counters: [0] triplets appended, [1] tracks appended, [2] status bits
+enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
+
+__device__ inline uint64_t lanemask_lt() {
+  const unsigned lane = threadIdx.x & 63u;
+  return lane ? (~0ull >> (64u - lane)) : 0ull;
+}
+
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ------------------------------------------------------------- cut tests
+// cos(Phi_ij) = (h_i . h_j) / (R_i R_j) in a closed window.
+__device__ inline bool cos_cut(float x0, float y0, float x1, float y1, float invRR, float lo, float hi,
+                               float Ra, float Rb) {
+  const float a = x0 * x1, b = y0 * y1;
+  const float c = (a + b) * invRR;
+  const float err = 8.0f * kU32 * (fabsf(a) + fabsf(b)) * invRR;
+  if (c - err > lo && c + err < hi) return true;
+  if (c + err < lo || c - err > hi) return false;
+  const double cd = ((double)x0 * x1 + (double)y0 * y1) / ((double)Ra * (double)Rb);
+  return cd >= (double)lo && cd <= (double)hi;
+}
+
+// Delta lambda = tan(lambda_12) - tan(lambda_01) in a closed window.
+__device__ inline bool dl_cut(float z0, float z1, float z2, float t12, const Consts& C) {
+  const float t01 = (z1 - z0) * C.inv01;
+  const float dl = t12 - t01;
+  const float err = 8.0f * kU32 * (fabsf(t01) + fabsf(t12) + fabsf(dl));
+  if (dl - err > C.dl_lo && dl + err < C.dl_hi) return true;
+  if (dl + err < C.dl_lo || dl - err > C.dl_hi) return false;
+  const double d = ((double)z2 - (double)z1) / ((double)C.R[2] - (double)C.R[1]) -
+                   ((double)z1 - (double)z0) / ((double)C.R[1] - (double)C.R[0]);
+  return d >= (double)C.dl_lo && d <= (double)C.dl_hi;
+}
+
+// |r_tc| in a closed window, tested as r_tc^2 = d01^2 d12^2 d20^2 / (4 cross^2)
+// with bounds on the rounding of the cross product and the chords.
+__device__ inline bool rtc_cut(float x0, float y0, float x1, float y1, float x2, float y2, const Consts& C) {
+  const float ax = x0 - x1, ay = y0 - y1, bx = x2 - x1, by = y2 - y1, ex = x2 - x0, ey = y2 - y0;
+  const float pa = ax * by, pb = ay * bx;
+  const float cr = fabsf(pa - pb);
+  const float ecr = 8.0f * kU32 * (fabsf(pa) + fabsf(pb));
+  const float num = (ax * ax + ay * ay) * (bx * bx + by * by) * (ex * ex + ey * ey);
+  const float en = 32.0f * kU32;
+  const float clo = fmaxf(cr - ecr, 0.0f), chi = cr + ecr;
+  const float dlo = 4.0f * clo * clo, dhi = 4.0f * chi * chi;
+  const float nlo = num * (1.0f - en), nhi = num * (1.0f + en);
+  const float m = 1.0f + 16.0f * kU32;
+  const float lo2 = C.rtc_lo2, hi2 = C.rtc_hi2;
+  if (dlo > 0.0f && nlo >= lo2 * dhi * m && nhi * m <= hi2 * dlo) return true;
+  if (nhi * m < lo2 * dlo || nlo > hi2 * dhi * m) return false;
+  const double dax = (double)x0 - x1, day = (double)y0 - y1, dbx = (double)x2 - x1, dby = (double)y2 - y1;
+  const double dex = (double)x2 - x0, dey = (double)y2 - y0;
+  const double cross = dax * dby - day * dbx;
+  if (cross == 0.0) return false;
+  const double r = sqrt(dax * dax + day * day) * sqrt(dbx * dbx + dby * dby) * sqrt(dex * dex + dey * dey) /
+                   (2.0 * fabs(cross));
+  return r >= (double)C.rtc_lo && r <= (double)C.rtc_hi;
+}
+
+// =================================================================== k_cuts
+__global__ void __launch_bounds__(64)
+k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+       const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
+       int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ head,
+       int32_t* __restrict__ ccnt, int32_t* __restrict__ trips, int trip_cap,
+       int32_t* __restrict__ counters) {
+  __shared__ float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
+  __shared__ unsigned long long sm01[2 * kMaxLayerHits];
+  __shared__ uint32_t spend[2 * kWave];
+  __shared__ uint32_t stb[kTripBuf];
+  const int lane = threadIdx.x;
+  const bool stream = C.max_trip > kStreamAbove;
+
+  for (int f = blockIdx.x; f < F; f += gridDim.x) {
+    const int b0 = lo[4 * f], b1 = lo[4 * f + 1], b2 = lo[4 * f + 2], b3 = lo[4 * f + 3], b4 = lo[4 * f + 4];
+    const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2, n3 = b4 - b3;
+    if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
+    if (lane == 0) { head[f] = -1; ccnt[f] = 0; counts[3 * f + 1] = 0; counts[3 * f + 2] = 0; }
+    if (b0 < 0 || n0 < 0 || n1 < 0 || n2 < 0 || n3 < 0 || b4 > n_hits) {
+      // malformed offsets: nothing of this frame is read
+      if (lane == 0) { flags[f] = 0; counts[3 * f] = 0; atomicOr(&counters[2], ST_BAD_OFFSETS); }
+      continue;
+    }
+    if (n0 > C.max_lh || n1 > C.max_lh || n2 > C.max_lh || n3 > C.max_lh) {
+      if (lane == 0) { flags[f] = MU3E_HITS_OVF | MU3E_KEEP; counts[3 * f] = 0; }
+      continue;
+    }
+    // ---- stage the layer-0..2 hits of the frame (coalesced)
+    const int n012 = n0 + n1 + n2;
+    for (int i = lane; i < n012; i += kWave) {
+      const int l = (i >= n0) + (i >= n0 + n1);
+      const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
+      sx[l * kMaxLayerHits + k] = X[b0 + i];
+      sy[l * kMaxLayerHits + k] = Y[b0 + i];
+      sz[l * kMaxLayerHits + k] = Z[b0 + i];
+    }
+    __syncthreads();
+    // ---- layer-0 partners of every layer-1 hit (Phi01 window)
+    for (int i1 = lane; i1 < n1; i1 += kWave) {
+      const float x1 = sx[kMaxLayerHits + i1], y1 = sy[kMaxLayerHits + i1];
+      unsigned long long w0 = 0, w1 = 0;
+      for (int i0 = 0; i0 < n0; ++i0) {
+        const bool p = cos_cut(sx[i0], sy[i0], x1, y1, C.invRR01, C.c01_lo, C.c01_hi, C.R[0], C.R[1]);
+        if (p) { if (i0 < 64) w0 |= 1ull << i0; else w1 |= 1ull << (i0 - 64); }
+      }
+      sm01[2 * i1] = w0;
+      sm01[2 * i1 + 1] = w1;
+    }
+    __syncthreads();
+
+    int total = 0;   // triplets passing all cuts (exact)
+    int fill = 0;    // entries in the LDS buffer
+    auto flush = [&]() {
+      if (fill == 0) return;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&counters[0], fill);
+      base = __shfl(base, 0, 64);
+      for (int j = lane; j < fill; j += kWave) {
+        const int g = base + j;
+        if (g < trip_cap) { trips[2 * g] = f; trips[2 * g + 1] = (int32_t)stb[j]; }
+      }
+      if (lane == 0 && base + fill > trip_cap) atomicOr(&counters[2], ST_TRIP_FULL);
+      fill = 0;
+      __syncthreads();
+    };
+    // join k pending (h1, h2) pairs, lane j taking pair j, against the
+    // layer-0 partners of its h1
+    auto join = [&](int k) {
+      const bool have = lane < k;
+      const uint32_t e = have ? spend[lane] : 0u;
+      const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
+      const float x1 = sx[kMaxLayerHits + i1], y1 = sy[kMaxLayerHits + i1], z1 = sz[kMaxLayerHits + i1];
+      const float x2 = sx[2 * kMaxLayerHits + i2], y2 = sy[2 * kMaxLayerHits + i2], z2 = sz[2 * kMaxLayerHits + i2];
+      const float t12 = (z2 - z1) * C.inv12;
+      unsigned long long w0 = have ? sm01[2 * i1] : 0ull, w1 = have ? sm01[2 * i1 + 1] : 0ull;
+      const int nb = __popcll(w0) + __popcll(w1);
+      const int nmax = wave_max(nb);
+      for (int it = 0; it < nmax; ++it) {
+        if (stream && fill > kTripBuf - kWave) flush();
+        const bool act = it < nb;
+        int i0 = 0;
+        if (act) {
+          if (w0) { i0 = __ffsll((long long)w0) - 1; w0 &= w0 - 1; }
+          else { i0 = 64 + __ffsll((long long)w1) - 1; w1 &= w1 - 1; }
+        }
+        bool pass = false;
+        if (act) {
+          const float x0 = sx[i0], y0 = sy[i0], z0 = sz[i0];
+          pass = dl_cut(z0, z1, z2, t12, C) && rtc_cut(x0, y0, x1, y1, x2, y2, C);
+        }
+        const unsigned long long bm = __ballot(pass);
+        if (pass) {
+          const int slot = fill + __popcll(bm & lanemask_lt());
+          if (slot < kTripBuf) stb[slot] = (uint32_t)i0 | ((uint32_t)i1 << 8) | ((uint32_t)i2 << 16);
+        }
+        const int np = __popcll(bm);
+        fill += np;
+        total += np;
+      }
+      __syncthreads();
+    };
+
+    // ---- stream (h1, h2) pairs passing Phi12 into the join
+    int npend = 0;
+    if (n0 > 0 && n2 > 0) {
+      for (int i1 = 0; i1 < n1; ++i1) {
+        if ((sm01[2 * i1] | sm01[2 * i1 + 1]) == 0ull) continue;
+        const float x1 = sx[kMaxLayerHits + i1], y1 = sy[kMaxLayerHits + i1];
+        for (int base = 0; base < n2; base += kWave) {
+          const int i2 = base + lane;
+          bool p = false;
+          if (i2 < n2)
+            p = cos_cut(x1, y1, sx[2 * kMaxLayerHits + i2], sy[2 * kMaxLayerHits + i2], C.invRR12, C.c12_lo,
+                        C.c12_hi, C.R[1], C.R[2]);
+          const unsigned long long bm = __ballot(p);
+          if (p) spend[npend + __popcll(bm & lanemask_lt())] = (uint32_t)i1 | ((uint32_t)i2 << 8);
+          npend += __popcll(bm);
+          if (npend >= kWave) {
+            __syncthreads();
+            join(kWave);
+            const int rem = npend - kWave;
+            const uint32_t v = lane < rem ? spend[kWave + lane] : 0u;
+            __syncthreads();
+            if (lane < rem) spend[lane] = v;
+            __syncthreads();
+            npend = rem;
+          }
+        }
+      }
+      if (npend > 0) { __syncthreads(); join(npend); }
+    }
+    const bool ovf = total > C.max_trip;
+    if (stream || !ovf) flush();
+    if (lane == 0) {
+      counts[3 * f] = total;
+      flags[f] = ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u;
+    }
+    __syncthreads();
+  }
+}
+
+// ================================================================= k_tracks
+// Track reconstruction of one selected triplet (Section IV-B, Alg. 3).
+// Returns 1 accepted, 0 rejected, -1 undecided in float32 (re-evaluate).
+template <class T>
+__device__ inline int track_eval(const float* __restrict__ X, const float* __restrict__ Y,
+                                 const float* __restrict__ Z, int g0, int g1, int g2, int b3, int b4,
+                                 const Consts& C, int& g3, T& kbar, T& chi2) {
+  constexpr bool F32 = sizeof(T) == 4;
+  const float x0 = X[g0], y0 = Y[g0], z0 = Z[g0];
+  const float x1 = X[g1], y1 = Y[g1], z1 = Z[g1];
+  const float x2 = X[g2], y2 = Y[g2], z2 = Z[g2];
+  const Fit<T> f1 = fit_triplet<T>(x0, y0, z0, x1, y1, z1, x2, y2, z2, C);
+  if (!f1.ok) return (F32 && f1.c.cross != 0.0) ? -1 : 0;
+  T px = 0, py = 0, pz = 0;
+  bool near = false;
+  const int reach = predict_l3<T>(f1, x2, y2, z2, (T)C.R[3], (T)1e-4, px, py, pz, F32 ? &near : nullptr);
+  if (F32 && near) return -1;
+  if (!reach) return 0;
+  T best = (T)1e30, second = (T)1e30;
+  int ib = -1;
+  for (int g = b3; g < b4; ++g) {
+    const T dx = (T)X[g] - px, dy = (T)Y[g] - py, dz = (T)Z[g] - pz;
+    const T d2 = dx * dx + dy * dy + dz * dz;
+    if (d2 < best) { second = best; best = d2; ib = g; }
+    else if (d2 < second) second = d2;
+  }
+  if (ib < 0) return 0;
+  if (F32 && second < (T)1e29) {
+    const T eps = (T)1e-3;   // bound on the float32 error of the predicted point [mm]
+    if (second - best <= (T)2 * eps * (m_sqrt(best) + m_sqrt(second)) + (T)1e-5 * second) return -1;
+  }
+  g3 = ib;
+  const Fit<T> f2 = fit_triplet<T>(x1, y1, z1, x2, y2, z2, X[ib], Y[ib], Z[ib], C);
+  if (!f2.ok) return (F32 && f2.c.cross != 0.0) ? -1 : 0;
+  if (f2.c.sgn != f1.c.sgn) return 0;
+  combine(f1, f2, kbar, chi2);
+  if (F32 && m_abs(chi2 - (T)C.chi2_trk) <= (T)0.1) return -1;
+  return chi2 < (T)C.chi2_trk ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+         const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags,
+         const int32_t* __restrict__ trips, int trip_cap, int32_t* __restrict__ counts,
+         int32_t* __restrict__ head, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
+         int32_t* __restrict__ counters) {
+  const int n = min(counters[0], trip_cap);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int f = trips[2 * t];
+    if (flags[f] & MU3E_TRIPLET_OVF) continue;
+    const uint32_t pk = (uint32_t)trips[2 * t + 1];
+    const int g0 = lo[4 * f] + (int)(pk & 0xff);
+    const int g1 = lo[4 * f + 1] + (int)((pk >> 8) & 0xff);
+    const int g2 = lo[4 * f + 2] + (int)((pk >> 16) & 0xff);
+    const int b3 = lo[4 * f + 3], b4 = lo[4 * f + 4];
+    int g3 = -1;
+    float kb = 0.f, c2 = 0.f;
+    int r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
+    if (r < 0) {
+      double kd = 0, cd = 0;
+      r = track_eval<double>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kd, cd);
+      kb = (float)kd;
+      c2 = (float)cd;
+    }
+    if (r != 1) continue;
+    atomicAdd(&counts[3 * f + 1], 1);
+    atomicAdd(&ccnt[f], kb > 0.f ? 1 : 65536);
+    const int slot = atomicAdd(&counters[1], 1);
+    if (slot >= trk_cap) { atomicOr(&counters[2], ST_TRACK_FULL); continue; }
+    int32_t* o = trk + 8 * slot;
+    o[0] = f; o[1] = g0; o[2] = g1; o[3] = g2; o[4] = g3;
+    o[6] = __float_as_int(kb);
+    o[7] = __float_as_int(c2);
+    o[5] = atomicExch(&head[f], slot);
+  }
+}
+
+// ================================================================ vertex
+// Per-track quantities of the vertex stage, in float64 (Section IV-C).
+struct VTrack {
+  double q, E, p, cth, rt, cx, cy, rbar, sms0, hx, hy, hz;
+};
+
+// Refit of a four-hit track in float64 and its transverse circle: radius
+// r_t = Rbar sin(theta_C1), centre on the bending side of the layer-0/1 chord.
+__device__ inline bool vtrack_make(const float* __restrict__ X, const float* __restrict__ Y,
+                                   const float* __restrict__ Z, int n_hits, const int32_t* h, const Consts& C,
+                                   VTrack& v) {
+  const int g0 = h[0], g1 = h[1], g2 = h[2], g3 = h[3];
+  if ((unsigned)g0 >= (unsigned)n_hits || (unsigned)g1 >= (unsigned)n_hits || (unsigned)g2 >= (unsigned)n_hits ||
+      (unsigned)g3 >= (unsigned)n_hits)
+    return false;
+  const Fit<double> a = fit_triplet<double>(X[g0], Y[g0], Z[g0], X[g1], Y[g1], Z[g1], X[g2], Y[g2], Z[g2], C);
+  const Fit<double> b = fit_triplet<double>(X[g1], Y[g1], Z[g1], X[g2], Y[g2], Z[g2], X[g3], Y[g3], Z[g3], C);
+  if (!a.ok || !b.ok) return false;
+  double kbar, chi2;
+  combine(a, b, kbar, chi2);
+  v.q = kbar > 0 ? 1.0 : -1.0;
+  v.rbar = 1.0 / fabs(kbar);
+  v.p = kCLight * (double)C.b * v.rbar;
+  v.E = sqrt(v.p * v.p + kMassE * kMassE);
+  v.cth = cos(a.th1);
+  const double sth = sin(a.th1);
+  v.hx = X[g0]; v.hy = Y[g0]; v.hz = Z[g0];
+  const double dx = (double)X[g1] - v.hx, dy = (double)Y[g1] - v.hy;
+  const double d = sqrt(dx * dx + dy * dy);
+  double rt = v.rbar * sth;
+  if (rt < 0.5 * d) rt = 0.5 * d;
+  v.rt = rt;
+  const double off = sqrt(fmax(rt * rt - 0.25 * d * d, 0.0));
+  // right-hand normal of the motion h0 -> h1 is (dy, -dx)/d; clockwise
+  // (positive) tracks curve to the right
+  v.cx = 0.5 * (v.hx + X[g1]) + v.q * off * dy / d;
+  v.cy = 0.5 * (v.hy + Y[g1]) - v.q * off * dx / d;
+  v.sms0 = highland<double>(v.p, (double)C.xx0 / sth);
+  return true;
+}
+
+// Turning angle travelled backwards along the track from its layer-0 hit to
+// the point q, in [0, 2 pi).
+__device__ inline double back_turn(const VTrack& t, double qx, double qy) {
+  const double vx = t.hx - t.cx, vy = t.hy - t.cy, wx = qx - t.cx, wy = qy - t.cy;
+  double a = atan2(vx * wy - vy * wx, vx * wx + vy * wy);   // counter-clockwise h0 -> q
+  if (t.q < 0) a = -a;                                       // backwards of a clockwise track is ccw
+  if (a < 0) a += 2.0 * kPiD;
+  return a;
+}
+
+__device__ inline double sigma2_at(const VTrack& t, double qx, double qy, const Consts& C) {
+  const double s = t.rt * back_turn(t, qx, qy);
+  return t.sms0 * t.sms0 * s * s + (double)C.sig_pix * (double)C.sig_pix;
+}
+
+__device__ inline double cone_dist(double r, double z, const Consts& C) {
+  // distance in the (r, z) half plane to the segments (R_t, 0) - (0, +-50)
+  double best = 1e300;
+  for (int s = -1; s <= 1; s += 2) {
+    const double ux = -(double)C.r_target, uz = 50.0 * s;
+    const double px = r - (double)C.r_target, pz = z;
+    double t = (px * ux + pz * uz) / (ux * ux + uz * uz);
+    t = t < 0 ? 0 : (t > 1 ? 1 : t);
+    const double ex = px - t * ux, ez = pz - t * uz;
+    best = fmin(best, sqrt(ex * ex + ez * ez));
+  }
+  return best;
+}
+
+// Vertex estimate of one e+ e+ e- triple: returns true if a combination of
+// intersections passes all three signal tests; the minimum-chi2 passing
+// combination is returned in v[4].
+__device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C, double* v) {
+  const VTrack* tk[3] = {T0, T1, T2};
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  double qx[3][2], qy[3][2];
+  int nq[3];
+  const double lim = (double)C.r_target + (double)C.target_tol;
+  for (int k = 0; k < 3; ++k) {
+    const VTrack& A = *tk[pa[k]];
+    const VTrack& B = *tk[pb[k]];
+    const double dx = B.cx - A.cx, dy = B.cy - A.cy;
+    const double d = sqrt(dx * dx + dy * dy);
+    if (d == 0.0 || d > A.rt + B.rt || d < fabs(A.rt - B.rt)) return false;
+    const double a = (A.rt * A.rt - B.rt * B.rt + d * d) / (2.0 * d);
+    const double h = sqrt(fmax(A.rt * A.rt - a * a, 0.0));
+    const double ux = dx / d, uy = dy / d;
+    nq[k] = 0;
+    for (int s = -1; s <= 1; s += 2) {
+      const double x = A.cx + a * ux - s * h * uy, y = A.cy + a * uy + s * h * ux;
+      if (sqrt(x * x + y * y) <= lim) { qx[k][nq[k]] = x; qy[k][nq[k]] = y; ++nq[k]; }
+    }
+    if (nq[k] == 0) return false;
+  }
+  bool found = false;
+  for (int c = 0; c < 8; ++c) {
+    const int sel[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    if (sel[0] >= nq[0] || sel[1] >= nq[1] || sel[2] >= nq[2]) continue;
+    double w = 0, mx = 0, my = 0;
+    for (int k = 0; k < 3; ++k) {
+      const double x = qx[k][sel[k]], y = qy[k][sel[k]];
+      const double s2 = 0.5 * (sigma2_at(*tk[pa[k]], x, y, C) + sigma2_at(*tk[pb[k]], x, y, C));
+      w += 1.0 / s2; mx += x / s2; my += y / s2;
+    }
+    mx /= w; my /= w;
+    double px[3], py[3], pz[3], s2k[3];
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+      const VTrack& t = *tk[k];
+      const double ex = mx - t.cx, ey = my - t.cy;
+      const double en = sqrt(ex * ex + ey * ey);
+      if (en == 0.0) { ok = false; break; }
+      px[k] = t.cx + t.rt * ex / en;
+      py[k] = t.cy + t.rt * ey / en;
+      const double dphi = back_turn(t, px[k], py[k]);
+      pz[k] = t.hz - dphi * t.rbar * t.cth;
+      const double s = t.rt * dphi;
+      s2k[k] = t.sms0 * t.sms0 * s * s + (double)C.sig_pix * (double)C.sig_pix;
+    }
+    if (!ok) continue;
+    double wz = 0, mz = 0;
+    for (int k = 0; k < 3; ++k) { wz += 1.0 / s2k[k]; mz += pz[k] / s2k[k]; }
+    mz /= wz;
+    double chi2 = 0;
+    for (int k = 0; k < 3; ++k) {
+      const double ex = px[k] - mx, ey = py[k] - my, ez = pz[k] - mz;
+      chi2 += (ex * ex + ey * ey + ez * ez) / s2k[k];
+    }
+    const double dt = cone_dist(sqrt(mx * mx + my * my), mz, C);
+    double sx = 0, sy = 0, sz = 0;
+    for (int k = 0; k < 3; ++k) {
+      const VTrack& t = *tk[k];
+      const double ux = (px[k] - t.cx) / t.rt, uy = (py[k] - t.cy) / t.rt;
+      const double pt = kCLight * (double)C.b * t.rt;
+      // travel direction: clockwise (positive) -> (uy, -ux)
+      sx += pt * t.q * uy;
+      sy -= pt * t.q * ux;
+      sz += t.p * t.cth;
+    }
+    const double ps = sqrt(sx * sx + sy * sy + sz * sz);
+    if (chi2 <= (double)C.chi2_v && dt <= (double)C.d_target && ps <= (double)C.p_sum) {
+      if (!found || chi2 < v[3]) { v[0] = mx; v[1] = my; v[2] = mz; v[3] = chi2; }
+      found = true;
+    }
+  }
+  return found;
+}
+
+constexpr int kVtxTracks = 256;   // tracks of one frame staged in LDS for the vertex wave
+
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Vertex stage of one frame by one wave (Alg. 4): tracks split by charge,
+// lanes over the flat index of e+e+e- triples (unordered e+ pair, e-);
+// first the energy test and the combination cap, then the vertex estimate of
+// every energy-passing triple and a wave-wide minimum of the vertex chi2
+// (ties to the lowest triple index).  id(j) gives the j-th track slot.
+template <class Id>
+__device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict__ vt,
+                            const int32_t* __restrict__ vok, const Consts& C, uint32_t* __restrict__ flags,
+                            int32_t* __restrict__ ncombo, float* __restrict__ vtx) {
+  __shared__ int spos[kVtxTracks], sneg[kVtxTracks];
+  const int lane = threadIdx.x;
+  const double elo = kMassMu - (double)C.de_max, ehi = kMassMu + (double)C.de_max;
+  if (n > kVtxTracks) {
+    // more tracks than the LDS table holds (lifted caps): one lane, serially
+    if (lane == 0) {
+      long long cnt = 0;
+      for (int a = 0; a < n; ++a)
+        for (int b = a + 1; b < n; ++b)
+          for (int e = 0; e < n; ++e) {
+            const int ta = id(a), tb = id(b), te = id(e);
+            if (!vok[ta] || !vok[tb] || !vok[te] || vt[ta].q < 0 || vt[tb].q < 0 || vt[te].q > 0) continue;
+            const double s = vt[ta].E + vt[tb].E + vt[te].E;
+            cnt += (s >= elo && s <= ehi);
+          }
+      *ncombo = (int32_t)min(cnt, (long long)0x7fffffff);
+      if (cnt > C.max_combo) { *flags |= MU3E_COMBO_OVF | MU3E_KEEP; return; }
+      bool found = false;
+      double best[4] = {0, 0, 0, 0};
+      for (int a = 0; a < n; ++a)
+        for (int b = a + 1; b < n; ++b)
+          for (int e = 0; e < n; ++e) {
+            const int ta = id(a), tb = id(b), te = id(e);
+            if (!vok[ta] || !vok[tb] || !vok[te] || vt[ta].q < 0 || vt[tb].q < 0 || vt[te].q > 0) continue;
+            const double s = vt[ta].E + vt[tb].E + vt[te].E;
+            if (!(s >= elo && s <= ehi)) continue;
+            double v[4];
+            if (vertex_triple(&vt[ta], &vt[tb], &vt[te], C, v) && (!found || v[3] < best[3])) {
+              for (int k = 0; k < 4; ++k) best[k] = v[k];
+              found = true;
+            }
+          }
+      if (found) {
+        *flags |= MU3E_VERTEX | MU3E_KEEP;
+        for (int k = 0; k < 4; ++k) vtx[k] = (float)best[k];
+      }
+    }
+    return;
+  }
+  // ---- split by charge (ballot compaction)
+  int np = 0, nn = 0;
+  for (int base = 0; base < n; base += kWave) {
+    const int j = base + lane;
+    const int t = j < n ? id(j) : -1;
+    const bool ok = t >= 0 && vok[t];
+    const bool ps = ok && vt[t].q > 0, ng = ok && vt[t].q < 0;
+    const unsigned long long mp = __ballot(ps), mn = __ballot(ng);
+    if (ps) spos[np + __popcll(mp & lanemask_lt())] = t;
+    if (ng) sneg[nn + __popcll(mn & lanemask_lt())] = t;
+    np += __popcll(mp);
+    nn += __popcll(mn);
+  }
+  __syncthreads();
+  const int npair = np * (np - 1) / 2;
+  const int total = npair * nn;
+  auto decode = [&](int k, int& ta, int& tb, int& te) {
+    int q = k / nn;
+    te = sneg[k - q * nn];
+    int i = 0;
+    while (q >= np - 1 - i) { q -= np - 1 - i; ++i; }
+    ta = spos[i];
+    tb = spos[i + 1 + q];
+  };
+  // ---- energy test over all triples, combination cap
+  int cnt = 0;
+  for (int k = lane; k < total; k += kWave) {
+    int ta, tb, te;
+    decode(k, ta, tb, te);
+    const double s = vt[ta].E + vt[tb].E + vt[te].E;
+    cnt += (s >= elo && s <= ehi);
+  }
+  cnt = wave_sum(cnt);
+  if (lane == 0) *ncombo = cnt;
+  if (cnt > C.max_combo) {
+    if (lane == 0) *flags |= MU3E_COMBO_OVF | MU3E_KEEP;
+    __syncthreads();
+    return;
+  }
+  // ---- vertex of every energy-passing triple
+  double best = 1e300;
+  int bestk = 0x7fffffff;
+  double bv[3] = {0, 0, 0};
+  if (cnt > 0) {
+    for (int k = lane; k < total; k += kWave) {
+      int ta, tb, te;
+      decode(k, ta, tb, te);
+      const double s = vt[ta].E + vt[tb].E + vt[te].E;
+      if (!(s >= elo && s <= ehi)) continue;
+      double v[4];
+      if (vertex_triple(&vt[ta], &vt[tb], &vt[te], C, v) && v[3] < best) {
+        best = v[3]; bestk = k; bv[0] = v[0]; bv[1] = v[1]; bv[2] = v[2];
+      }
+    }
+  }
+  // wave-wide minimum of (chi2, triple index)
+  double wb = best;
+  int wk = bestk;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(wb, o, 64);
+    const int ok = __shfl_xor(wk, o, 64);
+    if (ob < wb || (ob == wb && ok < wk)) { wb = ob; wk = ok; }
+  }
+  if (wk != 0x7fffffff && bestk == wk) {
+    *flags |= MU3E_VERTEX | MU3E_KEEP;
+    vtx[0] = (float)bv[0]; vtx[1] = (float)bv[1]; vtx[2] = (float)bv[2]; vtx[3] = (float)best;
+  }
+  __syncthreads();
+}
+
+// Frames able to form an e+e+e- triple (two e+ and one e- tracks, no
+// overflow so far) get a slice of the candidate track table; frames with
+// more than max_tracks tracks are flagged (Alg. 3: "marked for storage").
+__global__ void __launch_bounds__(256)
+k_vcand(int F, Consts C, uint32_t* __restrict__ flags, const int32_t* __restrict__ counts,
+        const int32_t* __restrict__ ccnt, int32_t* __restrict__ vbase, int32_t* __restrict__ vpos,
+        int32_t* __restrict__ cand, int32_t* __restrict__ counters) {
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x) {
+    vbase[f] = -1;
+    const uint32_t fl = flags[f];
+    if (fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF)) continue;
+    const int nt = counts[3 * f + 1];
+    if (nt > C.max_trk) { flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP; continue; }
+    const int cc = ccnt[f];
+    if ((cc & 0xffff) < 2 || (cc >> 16) < 1) continue;
+    const int c = atomicAdd(&counters[3], 1);
+    vbase[f] = atomicAdd(&counters[4], nt);
+    vpos[f] = 0;
+    cand[c] = f;
+  }
+}
+
+// Float64 vertex-stage quantities of the tracks of candidate frames, and the
+// frames' track tables.
+__global__ void __launch_bounds__(256)
+k_vprep_list(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits, Consts C,
+             const int32_t* __restrict__ trk, int trk_cap, const int32_t* __restrict__ counters,
+             const int32_t* __restrict__ vbase, int32_t* __restrict__ vpos, int32_t* __restrict__ ctab,
+             VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
+  const int n = min(counters[1], trk_cap);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int f = trk[8 * t];
+    const int b = vbase[f];
+    if (b < 0) continue;
+    vok[t] = vtrack_make(X, Y, Z, n_hits, trk + 8 * t + 1, C, vt[t]) ? 1 : 0;
+    const int pos = atomicAdd(&vpos[f], 1);
+    if (b + pos < trk_cap) ctab[b + pos] = t;
+  }
+}
+
+struct TableId {
+  const int32_t* tab; int base;
+  __device__ int operator()(int j) const { return tab[base + j]; }
+};
+struct RangeId {
+  int base;
+  __device__ int operator()(int j) const { return base + j; }
+};
+
+__global__ void __launch_bounds__(64)
+k_vframes_list(Consts C, const int32_t* __restrict__ counters, const int32_t* __restrict__ cand,
+               const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos,
+               const int32_t* __restrict__ ctab, int trk_cap, const VTrack* __restrict__ vt,
+               const int32_t* __restrict__ vok, uint32_t* __restrict__ flags, int32_t* __restrict__ counts,
+               float* __restrict__ vtx) {
+  const int nc = counters[3];
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int f = cand[c];
+    const int b = vbase[f], n = vpos[f];
+    if (b < 0 || b + n > trk_cap) continue;   // track list overflowed: reported in the status word
+    vertex_wave(f, n, TableId{ctab, b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_vprep_range(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
+              Consts C, const int32_t* __restrict__ hit, int n, VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    vok[t] = vtrack_make(X, Y, Z, n_hits, hit + 4 * t, C, vt[t]) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(64)
+k_vframes_range(int F, int n_tracks, Consts C, const int32_t* __restrict__ off, const VTrack* __restrict__ vt,
+                const int32_t* __restrict__ vok, uint32_t* __restrict__ flags, int32_t* __restrict__ combos,
+                float* __restrict__ vtx) {
+  const int lane = threadIdx.x;
+  for (int f = blockIdx.x; f < F; f += gridDim.x) {
+    if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
+    const int b = off[f], nt = off[f + 1] - off[f];
+    uint32_t fl = 0;
+    int32_t nc = 0;
+    const bool valid = b >= 0 && nt >= 0 && off[f + 1] <= n_tracks;   // malformed ranges: no triples
+    if (valid && nt > C.max_trk) fl = MU3E_TRACK_OVF | MU3E_KEEP;
+    __syncthreads();
+    if (valid && nt <= C.max_trk && nt >= 3) {
+      __shared__ uint32_t sfl;
+      __shared__ int32_t snc;
+      if (lane == 0) { sfl = 0; snc = 0; }
+      __syncthreads();
+      vertex_wave(f, nt, RangeId{b}, vt, vok, C, &sfl, &snc, vtx + 4 * f);
+      __syncthreads();
+      fl = sfl;
+      nc = snc;
+    }
+    if (lane == 0) { flags[f] = fl; combos[f] = nc; }
+    __syncthreads();
+  }
+}
+
+// ================================================================== k_fit
+__global__ void __launch_bounds__(256)
+k_fit(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
+      const int32_t* __restrict__ trip, int n, Consts C, float* __restrict__ out) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int g0 = trip[3 * t], g1 = trip[3 * t + 1], g2 = trip[3 * t + 2];
+    float* o = out + 8 * t;
+    const bool inb = (unsigned)g0 < (unsigned)n_hits && (unsigned)g1 < (unsigned)n_hits &&
+                     (unsigned)g2 < (unsigned)n_hits;
+    Fit<float> f;
+    f.ok = false;
+    if (inb) f = fit_triplet<float>(X[g0], Y[g0], Z[g0], X[g1], Y[g1], Z[g1], X[g2], Y[g2], Z[g2], C);
+    if (!f.ok) {
+      for (int k = 0; k < 8; ++k) o[k] = __builtin_nanf("");
+      continue;
+    }
+    o[0] = f.kappa; o[1] = f.s2kappa; o[2] = f.chi2; o[3] = f.rstar; o[4] = f.s2r;
+    o[5] = (float)f.c.sgn * f.c.rho; o[6] = f.th1; o[7] = f.th2;
+  }
+}
+
+
+// ============================================================== alignment
+// Summed triplet-fit chi2 under per-sensor alignment (tx, ty, tz, alpha):
+// a hit h on sensor s is moved to R_z(alpha_s) h + t_s (in float64) and the
+// triplet is fitted in float32 as in the track stage.
+constexpr int kAlignBlocks = 1024;
+constexpr int kAlignMaxSensors = 2048;   // float64 LDS accumulators per block
+
+__device__ inline void align_hit(const float* __restrict__ X, const float* __restrict__ Y,
+                                 const float* __restrict__ Z, const uint16_t* __restrict__ S,
+                                 const float* __restrict__ theta, int g, double* h, int& s, double& ca,
+                                 double& sa) {
+  s = S[g];
+  const double tx = theta[4 * s], ty = theta[4 * s + 1], tz = theta[4 * s + 2], a = theta[4 * s + 3];
+  ca = cos(a);
+  sa = sin(a);
+  const double x = X[g], y = Y[g];
+  h[0] = ca * x - sa * y + tx;
+  h[1] = sa * x + ca * y + ty;
+  h[2] = (double)Z[g] + tz;
+}
+
+__device__ inline bool align_triplet(const float* __restrict__ X, const float* __restrict__ Y,
+                                     const float* __restrict__ Z, const uint16_t* __restrict__ S, int n_hits,
+                                     int n_sensors, const float* __restrict__ theta, const int32_t* tr, double* h,
+                                     int* s, double* ca, double* sa) {
+  for (int k = 0; k < 3; ++k) {
+    const int g = tr[k];
+    if ((unsigned)g >= (unsigned)n_hits) return false;
+    if (S[g] >= n_sensors) return false;
+    align_hit(X, Y, Z, S, theta, g, h + 3 * k, s[k], ca[k], sa[k]);
+  }
+  return true;
+}
+
+__global__ void __launch_bounds__(256)
+k_align_fwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+            const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
+            const float* __restrict__ theta, int n_sensors, Consts C, float* __restrict__ chi2) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    double h[9], ca[3], sa[3];
+    int s[3];
+    float c = __builtin_nanf("");
+    if (align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, h, s, ca, sa)) {
+      const Fit<float> f = fit_triplet<float>(h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], h[8], C);
+      if (f.ok) c = f.chi2;
+    }
+    chi2[t] = c;
+  }
+}
+
+// Per block: sum over its triplets of grad_chi2[t] d chi2_t / d theta into
+// float64 LDS accumulators, then one partial row per block.
+__global__ void __launch_bounds__(256)
+k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+            const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
+            const float* __restrict__ theta, int n_sensors, Consts C, const float* __restrict__ gchi2,
+            double* __restrict__ partial) {
+  extern __shared__ double acc[];   // 4 * n_sensors float64 accumulators
+  const int np = 4 * n_sensors;
+  for (int j = threadIdx.x; j < np; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    double h[9], ca[3], sa[3];
+    int s[3];
+    if (!align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, h, s, ca, sa)) continue;
+    const float w = gchi2[t];
+    double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float c;
+    if (!fit_chi2_adjoint<float>(h, C, w, c, g)) continue;
+    for (int k = 0; k < 3; ++k) {
+      // hit before alignment: x = ca (x' - tx) + sa (y' - ty), y = -sa (x' - tx) + ca (y' - ty)
+      const double gx = g[3 * k], gy = g[3 * k + 1], gz = g[3 * k + 2];
+      const double x0 = X[trip[3 * t + k]], y0 = Y[trip[3 * t + k]];
+      const double dxa = -sa[k] * x0 - ca[k] * y0, dya = ca[k] * x0 - sa[k] * y0;   // d(x', y')/d alpha
+      double* a = acc + 4 * s[k];
+      atomicAdd(a + 0, gx);
+      atomicAdd(a + 1, gy);
+      atomicAdd(a + 2, gz);
+      atomicAdd(a + 3, gx * dxa + gy * dya);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < np; j += blockDim.x) partial[(size_t)blockIdx.x * np + j] = acc[j];
+}
+
+__global__ void __launch_bounds__(256)
+k_align_reduce(const double* __restrict__ partial, int blocks, int np, float* __restrict__ grad) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < np; j += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * np + j];
+    grad[j] = (float)s;
+  }
+}
+
+__global__ void k_zero(int32_t* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// =============================================================== host side
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t counters, trips, trk, vt, vok, ctab, head, ccnt, vbase, vpos, cand, total;
+};
+
+Layout layout(int64_t F, int64_t tc, int64_t kc) {
+  Layout L;
+  size_t o = 0;
+  L.counters = o; o += align256(kCounters * sizeof(int32_t));
+  L.trips = o; o += align256((size_t)tc * 2 * sizeof(int32_t));
+  L.trk = o; o += align256((size_t)kc * 8 * sizeof(int32_t));
+  L.vt = o; o += align256((size_t)kc * sizeof(VTrack));
+  L.vok = o; o += align256((size_t)kc * sizeof(int32_t));
+  L.ctab = o; o += align256((size_t)kc * sizeof(int32_t));
+  L.head = o; o += align256((size_t)F * sizeof(int32_t));
+  L.ccnt = o; o += align256((size_t)F * sizeof(int32_t));
+  L.vbase = o; o += align256((size_t)F * sizeof(int32_t));
+  L.vpos = o; o += align256((size_t)F * sizeof(int32_t));
+  L.cand = o; o += align256((size_t)F * sizeof(int32_t));
+  L.total = o;
+  return L;
+}
+
+bool make_consts(const mu3e_params_t* p, Consts& C) {
+  for (int i = 0; i < 4; ++i) { C.R[i] = p->r_layer[i]; C.zh[i] = p->z_half[i]; }
+  if (!(C.R[0] > 0 && C.R[1] > C.R[0] && C.R[2] > C.R[1] && C.R[3] > C.R[2])) return false;
+  C.b = p->b_tesla; C.xx0 = p->x_over_x0; C.sig_pix = p->sigma_pixel;
+  if (!(C.b > 0 && C.xx0 > 0 && C.sig_pix > 0)) return false;
+  C.dl_lo = p->dlambda.lo; C.dl_hi = p->dlambda.hi;
+  C.c01_lo = p->cosphi01.lo; C.c01_hi = p->cosphi01.hi;
+  C.c12_lo = p->cosphi12.lo; C.c12_hi = p->cosphi12.hi;
+  C.rtc_lo = p->rtc_abs.lo; C.rtc_hi = p->rtc_abs.hi;
+  if (!(C.dl_lo <= C.dl_hi && C.c01_lo <= C.c01_hi && C.c12_lo <= C.c12_hi && C.rtc_lo >= 0 &&
+        C.rtc_lo <= C.rtc_hi))
+    return false;
+  C.chi2_trk = p->chi2_track_max;
+  C.max_trip = p->max_triplets; C.max_trk = p->max_tracks; C.max_combo = p->max_combos;
+  C.max_lh = p->max_layer_hits;
+  if (C.max_trip < 0 || C.max_trk < 0 || C.max_combo < 0 || C.max_lh < 0) return false;
+  C.de_max = p->de_max; C.r_target = p->r_target; C.target_tol = p->target_tol;
+  C.chi2_v = p->chi2_vertex_max; C.d_target = p->d_target_max; C.p_sum = p->p_sum_max;
+  C.inv01 = 1.0f / (C.R[1] - C.R[0]);
+  C.inv12 = 1.0f / (C.R[2] - C.R[1]);
+  C.invRR01 = 1.0f / (C.R[0] * C.R[1]);
+  C.invRR12 = 1.0f / (C.R[1] * C.R[2]);
+  C.rtc_lo2 = C.rtc_lo * C.rtc_lo;
+  C.rtc_hi2 = C.rtc_hi * C.rtc_hi;
+  return true;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+bool hits_ok(const mu3e_hits_t* h) {
+  return h && h->n_frames >= 0 && h->n_hits >= 0 &&
+         (h->n_frames == 0 || (h->layer_offsets && (h->n_hits == 0 || (h->x && h->y && h->z))));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mu3e_status_string(mu3e_status s) {
+  switch (s) {
+    case MU3E_OK: return "ok";
+    case MU3E_ERR_INVALID_ARG: return "invalid argument";
+    case MU3E_ERR_HIP: return "HIP runtime error";
+    case MU3E_ERR_CAPACITY: return "workspace too small";
+    case MU3E_ERR_UNSUPPORTED: return "unsupported parameter";
+  }
+  return "unknown status";
+}
+
+size_t mu3e_select_workspace_size(int32_t n_frames, int32_t triplet_capacity, int32_t track_capacity) {
+  if (n_frames < 0 || triplet_capacity < 0 || track_capacity < 0) return 0;
+  return layout(n_frames, triplet_capacity, track_capacity).total;
+}
+
+mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
+                                     int32_t* frame_counts, float* frame_vertex, void* workspace,
+                                     size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
+                                     mu3e_debug_t* dbg, hipStream_t stream, hipEvent_t* ev) {
+  if (!hits_ok(hits) || !params || triplet_capacity < 0 || track_capacity < 0) return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (C.max_lh > kMaxLayerHits) return MU3E_ERR_UNSUPPORTED;
+  const int F = hits->n_frames;
+  const Layout L = layout(F, triplet_capacity, track_capacity);
+  if (!workspace || workspace_bytes < L.total) return MU3E_ERR_CAPACITY;
+  if (F > 0 && (!frame_flags || !frame_counts || !frame_vertex)) return MU3E_ERR_INVALID_ARG;
+  char* ws = static_cast<char*>(workspace);
+  int32_t* counters = reinterpret_cast<int32_t*>(ws + L.counters);
+  int32_t* trips = reinterpret_cast<int32_t*>(ws + L.trips);
+  int32_t* trk = reinterpret_cast<int32_t*>(ws + L.trk);
+  VTrack* vt = reinterpret_cast<VTrack*>(ws + L.vt);
+  int32_t* vok = reinterpret_cast<int32_t*>(ws + L.vok);
+  int32_t* ctab = reinterpret_cast<int32_t*>(ws + L.ctab);
+  int32_t* head = reinterpret_cast<int32_t*>(ws + L.head);
+  int32_t* ccnt = reinterpret_cast<int32_t*>(ws + L.ccnt);
+  int32_t* vbase = reinterpret_cast<int32_t*>(ws + L.vbase);
+  int32_t* vpos = reinterpret_cast<int32_t*>(ws + L.vpos);
+  int32_t* cand = reinterpret_cast<int32_t*>(ws + L.cand);
+  if (dbg) {
+    dbg->counters = counters; dbg->triplets = trips; dbg->tracks = trk;
+    dbg->triplet_capacity = triplet_capacity; dbg->track_capacity = track_capacity;
+  }
+  if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return MU3E_ERR_HIP;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, counters, kCounters);
+  if (F == 0) {
+    for (int k = 1; ev && k < 5; ++k) (void)hipEventRecord(ev[k], stream);
+    return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+  }
+  const int cus = device_cus();
+  const int g1 = F < cus * 16 ? F : cus * 16;
+  hipLaunchKernelGGL(k_cuts, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, F,
+                     hits->n_hits, C,
+                     frame_flags, frame_counts, frame_vertex, head, ccnt, trips, triplet_capacity, counters);
+  if (ev) (void)hipEventRecord(ev[1], stream);
+  hipLaunchKernelGGL(k_tracks, dim3(cus * 8), dim3(256), 0, stream, hits->x, hits->y, hits->z,
+                     hits->layer_offsets, C, frame_flags, trips, triplet_capacity, frame_counts, head, ccnt, trk,
+                     track_capacity, counters);
+  if (ev) (void)hipEventRecord(ev[2], stream);
+  const int gf = (F + 255) / 256 < cus * 8 ? (F + 255) / 256 : cus * 8;
+  hipLaunchKernelGGL(k_vcand, dim3(gf), dim3(256), 0, stream, F, C, frame_flags, frame_counts, ccnt, vbase, vpos, cand,
+                     counters);
+  hipLaunchKernelGGL(k_vprep_list, dim3(cus * 4), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->n_hits, C,
+                     trk, track_capacity, counters, vbase, vpos, ctab, vt, vok);
+  if (ev) (void)hipEventRecord(ev[3], stream);
+  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, C, counters, cand, vbase, vpos, ctab,
+                     track_capacity, vt, vok, frame_flags, frame_counts, frame_vertex);
+  if (ev) (void)hipEventRecord(ev[4], stream);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_select_frames(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
+                               int32_t* frame_counts, float* frame_vertex, void* workspace,
+                               size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
+                               mu3e_debug_t* dbg, hipStream_t stream) {
+  return mu3e_select_frames_timed(hits, params, frame_flags, frame_counts, frame_vertex, workspace,
+                                  workspace_bytes, triplet_capacity, track_capacity, dbg, stream, nullptr);
+}
+
+mu3e_status mu3e_fit_triplets(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const mu3e_params_t* params,
+                              float* out, hipStream_t stream) {
+  if (!hits || n < 0 || !params || (n > 0 && (!trip || !out || !hits->x || !hits->y || !hits->z)))
+    return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (n == 0) return MU3E_OK;
+  const int cus = device_cus();
+  const int blocks = (n + 255) / 256 < cus * 8 ? (n + 255) / 256 : cus * 8;
+  hipLaunchKernelGGL(k_fit, dim3(blocks), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->n_hits, trip, n, C,
+                     out);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+size_t mu3e_vertex_workspace_size(int32_t n_tracks) {
+  if (n_tracks < 0) return 0;
+  return align256((size_t)n_tracks * sizeof(VTrack)) + align256((size_t)n_tracks * sizeof(int32_t));
+}
+
+mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, const mu3e_params_t* params,
+                        uint32_t* frame_flags, int32_t* frame_combos, float* frame_vertex, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream) {
+  if (!hits || !tracks || !params || tracks->n_frames < 0 || tracks->n_tracks < 0) return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  const int F = tracks->n_frames, n = tracks->n_tracks;
+  if (F == 0) return MU3E_OK;
+  if (!tracks->frame_offsets || !frame_flags || !frame_combos || !frame_vertex ||
+      (n > 0 && (!tracks->hit || !hits->x || !hits->y || !hits->z)))
+    return MU3E_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < mu3e_vertex_workspace_size(n)) return MU3E_ERR_CAPACITY;
+  VTrack* vt = static_cast<VTrack*>(workspace);
+  int32_t* vok = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + align256((size_t)n * sizeof(VTrack)));
+  const int cus = device_cus();
+  if (n > 0) {
+    const int b = (n + 255) / 256 < cus * 8 ? (n + 255) / 256 : cus * 8;
+    hipLaunchKernelGGL(k_vprep_range, dim3(b), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->n_hits, C,
+                       tracks->hit, n, vt, vok);
+  }
+  const int g = F < cus * 16 ? F : cus * 16;
+  hipLaunchKernelGGL(k_vframes_range, dim3(g), dim3(kWave), 0, stream, F, n, C, tracks->frame_offsets, vt, vok,
+                     frame_flags, frame_combos, frame_vertex);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+size_t mu3e_align_workspace_size(int32_t n_sensors) {
+  if (n_sensors <= 0 || n_sensors > kAlignMaxSensors) return 0;
+  return align256((size_t)kAlignBlocks * 4 * n_sensors * sizeof(double));
+}
+
+static bool align_args_ok(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const float* theta,
+                          int32_t n_sensors) {
+  return hits && n >= 0 && n_sensors > 0 &&
+         (n == 0 || (trip && theta && hits->x && hits->y && hits->z && hits->sensor));
+}
+
+mu3e_status mu3e_align_chi2(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const float* theta,
+                            int32_t n_sensors, const mu3e_params_t* params, float* chi2, hipStream_t stream) {
+  if (!align_args_ok(hits, trip, n, theta, n_sensors) || !params || (n > 0 && !chi2)) return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (n_sensors > kAlignMaxSensors) return MU3E_ERR_UNSUPPORTED;
+  if (n == 0) return MU3E_OK;
+  const int cus = device_cus();
+  const int b = (n + 255) / 256 < cus * 8 ? (n + 255) / 256 : cus * 8;
+  hipLaunchKernelGGL(k_align_fwd, dim3(b), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->sensor,
+                     hits->n_hits, trip, n, theta, n_sensors, C, chi2);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const float* theta,
+                                int32_t n_sensors, const mu3e_params_t* params, const float* grad_chi2,
+                                float* grad_theta, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!align_args_ok(hits, trip, n, theta, n_sensors) || !params || !grad_theta || (n > 0 && !grad_chi2))
+    return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (n_sensors > kAlignMaxSensors) return MU3E_ERR_UNSUPPORTED;
+  if (!workspace || workspace_bytes < mu3e_align_workspace_size(n_sensors)) return MU3E_ERR_CAPACITY;
+  double* partial = static_cast<double*>(workspace);
+  const int np = 4 * n_sensors;
+  hipLaunchKernelGGL(k_align_bwd, dim3(kAlignBlocks), dim3(256), (size_t)np * sizeof(double), stream, hits->x, hits->y,
+                     hits->z, hits->sensor,
+                     hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial);
+  hipLaunchKernelGGL(k_align_reduce, dim3((np + 255) / 256), dim3(256), 0, stream, partial, kAlignBlocks, np,
+                     grad_theta);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+}  // extern "C"

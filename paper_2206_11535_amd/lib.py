@@ -1,0 +1,337 @@
+"""Python binding of the C ABI (include/mu3e.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the
+selection runs in the HIP kernels of libmu3e.so.  There is no fallback: if the
+library is missing, importing the compute entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmu3e.so")
+
+KEEP, TRIPLET_OVF, TRACK_OVF, COMBO_OVF, VERTEX, HITS_OVF = 1, 2, 4, 8, 16, 32
+MAX_LAYER_HITS = 128
+STATUS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "workspace too small",
+          -4: "unsupported parameter"}
+
+
+class Mu3eError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class Window(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float), ("hi", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("r_layer", ctypes.c_float * 4), ("z_half", ctypes.c_float * 4),
+                ("b_tesla", ctypes.c_float), ("x_over_x0", ctypes.c_float), ("sigma_pixel", ctypes.c_float),
+                ("dlambda", Window), ("cosphi01", Window), ("cosphi12", Window), ("rtc_abs", Window),
+                ("chi2_track_max", ctypes.c_float),
+                ("max_triplets", ctypes.c_int32), ("max_tracks", ctypes.c_int32),
+                ("max_combos", ctypes.c_int32), ("max_layer_hits", ctypes.c_int32),
+                ("de_max", ctypes.c_float), ("r_target", ctypes.c_float), ("target_tol", ctypes.c_float),
+                ("chi2_vertex_max", ctypes.c_float), ("d_target_max", ctypes.c_float),
+                ("p_sum_max", ctypes.c_float)]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("layer", ctypes.c_void_p), ("sensor", ctypes.c_void_p),
+                ("layer_offsets", ctypes.c_void_p), ("n_frames", ctypes.c_int32),
+                ("n_hits", ctypes.c_int32)]
+
+
+class Tracks(ctypes.Structure):
+    _fields_ = [("hit", ctypes.c_void_p), ("frame_offsets", ctypes.c_void_p),
+                ("n_frames", ctypes.c_int32), ("n_tracks", ctypes.c_int32)]
+
+
+class Debug(ctypes.Structure):
+    _fields_ = [("counters", ctypes.c_void_p), ("triplets", ctypes.c_void_p), ("tracks", ctypes.c_void_p),
+                ("triplet_capacity", ctypes.c_int32), ("track_capacity", ctypes.c_int32)]
+
+
+def make_params(p: dict) -> Params:
+    s = Params()
+    for i in range(4):
+        s.r_layer[i] = p["r_layer"][i]
+        s.z_half[i] = p["z_half"][i]
+    s.b_tesla, s.x_over_x0, s.sigma_pixel = p["b_tesla"], p["x_over_x0"], p["sigma_pixel"]
+    for name in ("dlambda", "cosphi01", "cosphi12", "rtc_abs"):
+        w = getattr(s, name)
+        w.lo, w.hi = p[name]
+    s.chi2_track_max = p["chi2_track_max"]
+    s.max_triplets, s.max_tracks = int(p["max_triplets"]), int(p["max_tracks"])
+    s.max_combos, s.max_layer_hits = int(p["max_combos"]), int(p["max_layer_hits"])
+    for name in ("de_max", "r_target", "target_tol", "chi2_vertex_max", "d_target_max", "p_sum_max"):
+        setattr(s, name, p[name])
+    return s
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmu3e.so (after torch, so that the process has one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2206_11535_amd.build.build()")
+    import torch  # noqa: F401  -- load torch's HIP runtime first
+    L = ctypes.CDLL(path)
+    P, I, Z = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    L.mu3e_status_string.restype = ctypes.c_char_p
+    L.mu3e_status_string.argtypes = [ctypes.c_int]
+    L.mu3e_select_workspace_size.restype = Z
+    L.mu3e_select_workspace_size.argtypes = [I, I, I]
+    L.mu3e_select_frames.restype = ctypes.c_int
+    L.mu3e_select_frames.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Params), P, P, P, P, Z, I, I,
+                                     ctypes.POINTER(Debug), P]
+    L.mu3e_select_frames_timed.restype = ctypes.c_int
+    L.mu3e_select_frames_timed.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Params), P, P, P, P, Z, I, I,
+                                           ctypes.POINTER(Debug), P, P]
+    L.mu3e_fit_triplets.restype = ctypes.c_int
+    L.mu3e_fit_triplets.argtypes = [ctypes.POINTER(Hits), P, I, ctypes.POINTER(Params), P, P]
+    L.mu3e_vertex_workspace_size.restype = Z
+    L.mu3e_vertex_workspace_size.argtypes = [I]
+    L.mu3e_vertex.restype = ctypes.c_int
+    L.mu3e_vertex.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Tracks), ctypes.POINTER(Params), P, P, P, P, Z, P]
+    L.mu3e_align_chi2.restype = ctypes.c_int
+    L.mu3e_align_chi2.argtypes = [ctypes.POINTER(Hits), P, I, P, I, ctypes.POINTER(Params), P, P]
+    L.mu3e_align_workspace_size.restype = Z
+    L.mu3e_align_workspace_size.argtypes = [I]
+    L.mu3e_align_backward.restype = ctypes.c_int
+    L.mu3e_align_backward.argtypes = [ctypes.POINTER(Hits), P, I, P, I, ctypes.POINTER(Params), P, P, P, Z, P]
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise Mu3eError(st, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceHits:
+    """Hits resident on the GPU (torch tensors) plus the ABI struct."""
+    x: object
+    y: object
+    z: object
+    layer: object
+    sensor: object
+    layer_offsets: object
+    n_frames: int
+    n_hits: int
+
+    def struct(self) -> Hits:
+        return Hits(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
+                    self.layer.data_ptr() if self.layer is not None else None,
+                    self.sensor.data_ptr() if self.sensor is not None else None,
+                    self.layer_offsets.data_ptr(), self.n_frames, self.n_hits)
+
+
+def to_device(fs, device="cuda") -> DeviceHits:
+    import torch
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt, copy=False)).to(device)
+    layer = t(fs.layer.astype(np.int16), np.int16) if getattr(fs, "layer", None) is not None else None
+    sensor = t(fs.sensor.astype(np.int16), np.int16) if getattr(fs, "sensor", None) is not None else None
+    return DeviceHits(t(fs.x, np.float32), t(fs.y, np.float32), t(fs.z, np.float32), layer, sensor,
+                      t(fs.layer_offsets, np.int32), int(fs.n_frames), int(len(fs.x)))
+
+
+class Selector:
+    """Preallocated outputs and workspace for repeated mu3e_select_frames calls."""
+
+    def __init__(self, n_frames: int, params: dict, triplet_capacity: int | None = None,
+                 track_capacity: int | None = None, device="cuda"):
+        import torch
+        L = load()
+        self.n_frames = n_frames
+        self.params = make_params(params)
+        self.tcap = int(triplet_capacity if triplet_capacity is not None else 64 * n_frames + 4096)
+        self.kcap = int(track_capacity if track_capacity is not None else 16 * n_frames + 4096)
+        nb = L.mu3e_select_workspace_size(n_frames, self.tcap, self.kcap)
+        if nb == 0 and n_frames > 0:
+            raise Mu3eError(-1, "mu3e_select_workspace_size")
+        self.ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+        self.flags = torch.empty(max(n_frames, 1), dtype=torch.int32, device=device)
+        self.counts = torch.empty((max(n_frames, 1), 3), dtype=torch.int32, device=device)
+        self.vertex = torch.empty((max(n_frames, 1), 4), dtype=torch.float32, device=device)
+        self.dbg = Debug()
+
+    def run(self, hits: DeviceHits, stream=None, events=None):
+        """events: optional ctypes array of 5 hipEvent_t recorded between the
+        stage kernels."""
+        L = load()
+        assert hits.n_frames == self.n_frames
+        hs = hits.struct()
+        if events is None:
+            st = L.mu3e_select_frames(ctypes.byref(hs), ctypes.byref(self.params), _ptr(self.flags),
+                                      _ptr(self.counts), _ptr(self.vertex), _ptr(self.ws), self.ws.numel(),
+                                      self.tcap, self.kcap, ctypes.byref(self.dbg), _stream(stream))
+        else:
+            st = L.mu3e_select_frames_timed(ctypes.byref(hs), ctypes.byref(self.params), _ptr(self.flags),
+                                            _ptr(self.counts), _ptr(self.vertex), _ptr(self.ws),
+                                            self.ws.numel(), self.tcap, self.kcap, ctypes.byref(self.dbg),
+                                            _stream(stream), ctypes.cast(events, ctypes.c_void_p))
+        _check(st, "mu3e_select_frames")
+
+    def counters(self):
+        """[triplets appended, tracks appended, status bits] (synchronises)."""
+        import torch
+        n = 3
+        base = self.dbg.counters - self.ws.data_ptr()
+        return self.ws[base:base + 4 * n].view(torch.int32).cpu().numpy()
+
+    def lists(self, hits_offsets: np.ndarray):
+        """Host copies of the triplet and track lists (global hit indices)."""
+        import torch
+        c = self.counters()
+        nt, nk = min(int(c[0]), self.tcap), min(int(c[1]), self.kcap)
+        ws = self.ws
+        tb = self.dbg.triplets - ws.data_ptr()
+        kb = self.dbg.tracks - ws.data_ptr()
+        trips = ws[tb:tb + 8 * nt].view(torch.int32).cpu().numpy().reshape(-1, 2)
+        trk = ws[kb:kb + 32 * nk].view(torch.int32).cpu().numpy().reshape(-1, 8)
+        lo = np.asarray(hits_offsets)
+        f = trips[:, 0].astype(np.int64)
+        pk = trips[:, 1].astype(np.int64)
+        g = np.stack([lo[4 * f] + (pk & 0xff), lo[4 * f + 1] + ((pk >> 8) & 0xff),
+                      lo[4 * f + 2] + ((pk >> 16) & 0xff)], 1)
+        triplets = np.concatenate([f[:, None], g], 1)
+        tracks = trk[:, [0, 1, 2, 3, 4]].astype(np.int64)
+        kf = trk[:, 6:8].copy().view(np.float32)
+        return triplets, tracks, kf, c
+
+    def result(self):
+        F = self.n_frames
+        return (self.flags[:F].cpu().numpy().view(np.uint32), self.counts[:F].cpu().numpy(),
+                self.vertex[:F].cpu().numpy())
+
+
+def select_frames(hits: DeviceHits, params: dict, stream=None, **kw):
+    s = Selector(hits.n_frames, params, **kw)
+    s.run(hits, stream)
+    return s
+
+
+def fit_triplets(hits: DeviceHits, trip, params: dict, stream=None):
+    """trip: int32 cuda tensor [n, 3] of global hit indices -> float32 [n, 8]."""
+    import torch
+    L = load()
+    n = int(trip.shape[0])
+    out = torch.empty((max(n, 1), 8), dtype=torch.float32, device=trip.device)
+    hs = hits.struct()
+    pp = make_params(params)
+    _check(L.mu3e_fit_triplets(ctypes.byref(hs), _ptr(trip), n, ctypes.byref(pp), _ptr(out), _stream(stream)),
+           "mu3e_fit_triplets")
+    return out[:n]
+
+
+def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=None):
+    """track_hits int32 [n, 4], frame_offsets int32 [F+1] (cuda tensors) ->
+    (flags [F], combos [F], vertex [F, 4])."""
+    import torch
+    L = load()
+    F = int(frame_offsets.shape[0]) - 1
+    n = int(track_hits.shape[0])
+    dev = frame_offsets.device
+    flags = torch.empty(max(F, 1), dtype=torch.int32, device=dev)
+    combos = torch.empty(max(F, 1), dtype=torch.int32, device=dev)
+    vtx = torch.empty((max(F, 1), 4), dtype=torch.float32, device=dev)
+    nb = L.mu3e_vertex_workspace_size(n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    hs = hits.struct()
+    tr = Tracks(track_hits.data_ptr() if n else None, frame_offsets.data_ptr(), F, n)
+    pp = make_params(params)
+    _check(L.mu3e_vertex(ctypes.byref(hs), ctypes.byref(tr), ctypes.byref(pp), _ptr(flags), _ptr(combos),
+                         _ptr(vtx), _ptr(ws), ws.numel(), _stream(stream)), "mu3e_vertex")
+    return flags[:F], combos[:F], vtx[:F]
+
+
+def align_chi2(hits: DeviceHits, trip, theta, params: dict, stream=None):
+    """Triplet-fit chi2 [n] after per-sensor alignment theta [S, 4] (float32
+    cuda tensors; trip int32 [n, 3])."""
+    import torch
+    L = load()
+    n = int(trip.shape[0])
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=theta.device)
+    hs = hits.struct()
+    pp = make_params(params)
+    _check(L.mu3e_align_chi2(ctypes.byref(hs), _ptr(trip), n, _ptr(theta), int(theta.shape[0]), ctypes.byref(pp),
+                             _ptr(out), _stream(stream)), "mu3e_align_chi2")
+    return out[:n]
+
+
+def align_backward(hits: DeviceHits, trip, theta, params: dict, grad_chi2, stream=None):
+    """d(sum_t grad_chi2[t] chi2_t) / d theta, float32 [S, 4]."""
+    import torch
+    L = load()
+    n = int(trip.shape[0])
+    S = int(theta.shape[0])
+    nb = L.mu3e_align_workspace_size(S)
+    if nb == 0:
+        raise Mu3eError(-4, "mu3e_align_workspace_size")
+    ws = torch.empty(nb, dtype=torch.uint8, device=theta.device)
+    g = torch.empty((S, 4), dtype=torch.float32, device=theta.device)
+    hs = hits.struct()
+    pp = make_params(params)
+    _check(L.mu3e_align_backward(ctypes.byref(hs), _ptr(trip), n, _ptr(theta), S, ctypes.byref(pp),
+                                 _ptr(grad_chi2), _ptr(g), _ptr(ws), ws.numel(), _stream(stream)),
+           "mu3e_align_backward")
+    return g
+
+
+def _autograd():
+    import torch
+
+    class AlignChi2(torch.autograd.Function):
+        """chi2[n] of frozen triplets as a function of the per-sensor
+        alignment theta [S, 4] = (tx, ty, tz, alpha); backward is the
+        hand-written adjoint of the fit (mu3e_align_backward)."""
+
+        @staticmethod
+        def forward(ctx, theta, hits, trip, params):
+            theta = theta.detach().contiguous().float()
+            ctx.hits, ctx.trip, ctx.params = hits, trip, params
+            ctx.save_for_backward(theta)
+            return align_chi2(hits, trip, theta, params)
+
+        @staticmethod
+        def backward(ctx, grad_chi2):
+            (theta,) = ctx.saved_tensors
+            g = align_backward(ctx.hits, ctx.trip, theta, ctx.params, grad_chi2.contiguous().float())
+            return g, None, None, None
+
+    return AlignChi2
+
+
+_align_fn = None
+
+
+def align_chi2_autograd(theta, hits: DeviceHits, trip, params: dict):
+    """Differentiable chi2[n] (torch.autograd.Function around the C ABI)."""
+    global _align_fn
+    if _align_fn is None:
+        _align_fn = _autograd()
+    return _align_fn.apply(theta, hits, trip, params)

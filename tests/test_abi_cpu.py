@@ -1,0 +1,85 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/mu3e.h declares, and rejects bad arguments on the host before any
+launch (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mu3e.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2206_11535_amd import lib
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2206_11535_amd import build
+        build.build()
+    return lib.load()
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mu3e_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared()
+    assert {"mu3e_select_frames", "mu3e_fit_triplets", "mu3e_vertex"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    assert L.mu3e_status_string(0) == b"ok"
+    assert b"invalid" in L.mu3e_status_string(-1)
+    assert L.mu3e_status_string(-3) == b"workspace too small"
+
+
+def test_workspace_sizes(L):
+    assert L.mu3e_select_workspace_size(-1, 10, 10) == 0
+    a = L.mu3e_select_workspace_size(1000, 64000, 16000)
+    b = L.mu3e_select_workspace_size(2000, 64000, 16000)
+    assert 0 < a < b and a % 256 == 0
+    assert L.mu3e_vertex_workspace_size(-5) == 0
+    assert L.mu3e_vertex_workspace_size(100) > L.mu3e_vertex_workspace_size(10)
+
+
+def _hits(lib, F):
+    # dummy non-null device-pointer stand-ins: never dereferenced, every call
+    # below fails validation before any launch
+    return lib.Hits(16, 32, 48, None, None, 64, F, 10)
+
+
+def test_host_validation(L):
+    from paper_2206_11535_amd import lib
+    from paper_2206_11535_amd.params import default_params
+    p = lib.make_params(default_params())
+    dbg = lib.Debug()
+    h = _hits(lib, 5)
+    # null hits
+    assert L.mu3e_select_frames(None, ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10, None, None) == -1
+    # workspace too small
+    assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 16, 10, 10, None, None) == -3
+    # unsupported layer capacity
+    q = lib.make_params(default_params(max_layer_hits=129))
+    assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(q), 1, 1, 1, 1, 1 << 30, 10, 10, None, None) == -4
+    # inverted window, negative cap, bad radii
+    for bad in (dict(dlambda=(0.5, -0.5)), dict(max_tracks=-1), dict(r_layer=(25.0, 24.0, 73.0, 85.0))):
+        q = lib.make_params(default_params(**bad))
+        assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(q), 1, 1, 1, 1, 1 << 30, 10, 10,
+                                    ctypes.byref(dbg), None) == -1
+    # negative capacities / frames
+    assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, -1, 10, None, None) == -1
+    h2 = _hits(lib, -1)
+    assert L.mu3e_select_frames(ctypes.byref(h2), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10, None, None) == -1
+    # fit: negative n, null triplets
+    assert L.mu3e_fit_triplets(ctypes.byref(h), None, -1, ctypes.byref(p), None, None) == -1
+    assert L.mu3e_fit_triplets(ctypes.byref(h), None, 5, ctypes.byref(p), 1, None) == -1
+    # vertex: null tracks, too small workspace
+    assert L.mu3e_vertex(ctypes.byref(h), None, ctypes.byref(p), 1, 1, 1, 1, 1 << 20, None) == -1
+    tr = lib.Tracks(80, 96, 4, 1000)
+    assert L.mu3e_vertex(ctypes.byref(h), ctypes.byref(tr), ctypes.byref(p), 1, 1, 1, 1, 8, None) == -3

@@ -1,0 +1,246 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every case runs the same seeded inputs through libmu3e.so on the GPU and
+through the oracle on the CPU and compares with tests/parity.py: exact sets
+apart from oracle-marked ambiguous candidates (and descendants); float
+results within 1e-4 relative.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2206_11535_amd import synth
+from paper_2206_11535_amd.params import default_params, lifted_caps
+from parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_11535_amd import lib as L
+    L.load()
+    return L
+
+
+def run_both(L, fs, params, frames_subset=None, **kw):
+    print(f"case: {fs.n_frames} frames, {fs.n_hits} hits, caps "
+          f"{params['max_triplets']}/{params['max_tracks']}/{params['max_combos']}", flush=True)
+    import torch
+    dh = L.to_device(fs)
+    sel = L.select_frames(dh, params, **kw)
+    torch.cuda.synchronize()
+    flags, counts, vtx = sel.result()
+    trips, tracks, kf, c = sel.lists(fs.layer_offsets)
+    assert c[2] == 0, f"list capacity status {c}"
+    orc = oracle.run(fs, params)
+    return orc, flags, counts, vtx, trips, tracks, kf, sel
+
+
+def check(L, fs, params, what, **kw):
+    orc, flags, counts, vtx, trips, tracks, kf, _ = run_both(L, fs, params, **kw)
+    bad, stats = compare(orc, flags, counts, vtx, trips, tracks, kf)
+    print(what, stats, flush=True)
+    assert_parity(bad, stats, what)
+    return orc, flags, counts
+
+
+def test_cfg1_full(lib):
+    orc, flags, counts = check(lib, synth.generate(1), default_params(), "cfg1")
+    assert counts[:, 0].sum() > 1000 and counts[:, 1].sum() > 500 and (flags & 16).sum() > 5
+
+
+def test_cfg2_subset(lib):
+    check(lib, synth.generate(2, n_frames=3000), default_params(), "cfg2[:3000]")
+
+
+def test_cfg3_mixed_subset(lib):
+    check(lib, synth.generate(3, n_frames=3000), default_params(), "cfg3[:3000]")
+
+
+def test_cfg4_lifted_caps(lib):
+    fs = synth.generate(4, n_frames=120)
+    p = lifted_caps()
+    orc, flags, counts = check(lib, fs, p, "cfg4[:120] lifted", triplet_capacity=400 * 120,
+                               track_capacity=80 * 120)
+    assert counts[:, 0].sum() > 20000
+
+
+def test_triplet_stream_path(lib):
+    """Wide windows and a lifted triplet cap: thousands of survivors per
+    frame stream through the LDS buffer to the global list."""
+    from paper_2206_11535_amd.params import INT32_MAX
+    fs = synth.generate(4, n_frames=40)
+    p = default_params(dlambda=(-3.0, 3.0), cosphi01=(0.5, 2.0), max_triplets=INT32_MAX)
+    orc, flags, counts = check(lib, fs, p, "cfg4[:40] wide windows", triplet_capacity=60000 * 40,
+                               track_capacity=4000 * 40)
+    assert counts[:, 0].max() > 2000
+
+
+def test_cfg4_paper_caps(lib):
+    check(lib, synth.generate(4, n_frames=200), default_params(), "cfg4[:200] paper caps",
+          triplet_capacity=1000 * 200)
+
+
+@pytest.mark.parametrize("cap", ["max_triplets", "max_tracks", "max_combos"])
+@pytest.mark.parametrize("value", [0, 1])
+def test_caps_zero_one(lib, cap, value):
+    check(lib, synth.generate(1, n_frames=400), default_params(**{cap: value}), f"{cap}={value}")
+
+
+def test_layer_hit_overflow(lib):
+    fs = synth.generate(2, n_frames=500)
+    orc, flags, counts = check(lib, fs, default_params(max_layer_hits=10), "max_layer_hits=10")
+    assert (flags & 32).sum() > 10
+
+
+def test_empty_and_tiny_frames(lib):
+    from helpers import Frames
+    frames = [[[], [], [], []],
+              [[(25.0, 0.0, 1.0)], [], [(73.0, 0.0, 2.0)], []],
+              [[(25.0, 0.0, 1.0)], [(31.0, 0.5, 1.2)], [(73.0, 2.0, 2.0)], []],
+              [[], [], [], [(85.0, 0.0, 0.0)]]]
+    fs = Frames(frames)
+    check(lib, fs, default_params(), "tiny frames")
+
+
+def test_misaligned_frames(lib):
+    check(lib, synth.generate(5, n_frames=2000), default_params(), "cfg5[:2000]")
+
+
+def test_signal_only_frames(lib):
+    cfg = dataclasses.replace(synth.CONFIGS[1], lam=0.5, noise_per_layer=0, signal_frac=1.0)
+    orc, flags, counts = check(lib, synth.generate(cfg, n_frames=1500, salt=9), default_params(), "signal")
+    assert (flags & 16).sum() > 300
+
+
+def test_fit_triplets(lib):
+    import torch
+    fs = synth.generate(2, n_frames=3000)
+    tt, _, tab = synth.true_triplets(fs)
+    rng = np.random.default_rng(0)
+    # true triplets, second triplets (layers 1-3) and random combinations
+    t2 = tab[np.all(tab[:, 1:4] >= 0, axis=1)][:, 1:4]
+    lo = fs.layer_offsets
+    f = rng.integers(0, fs.n_frames, 4000)
+    ok = np.all([lo[4 * f + l + 1] > lo[4 * f + l] for l in range(3)], axis=0)
+    f = f[ok]
+    rnd = np.stack([rng.integers(lo[4 * f + l], lo[4 * f + l + 1]) for l in range(3)], 1)
+    trip = np.concatenate([tt, t2, rnd]).astype(np.int32)
+    print(f"case: fit_triplets n={len(trip)}", flush=True)
+    dh = lib.to_device(fs)
+    out = lib.fit_triplets(dh, torch.from_numpy(trip).cuda(), default_params()).cpu().numpy()
+    h = np.stack([np.stack([fs.x[trip[:, k]], fs.y[trip[:, k]], fs.z[trip[:, k]]], 1) for k in range(3)], 1)
+    ref, rok = oracle.fit(h.astype(np.float64), default_params())
+    assert np.all(np.isfinite(out[rok, 0]))
+    names = ["kappa", "sigma2_kappa", "chi2", "r_star", "sigma2_r", "rtc", "theta1", "theta2"]
+    for i, k in enumerate(names):
+        g, o = out[rok, i].astype(np.float64), ref[k][rok]
+        floor = 1.0 if k == "chi2" else 0.0
+        err = np.abs(g - o) / np.maximum(np.abs(o), floor)
+        assert np.max(err) <= 1e-4, (k, float(np.max(err)), int(np.argmax(err)))
+
+
+def test_vertex_entry_point(lib):
+    """mu3e_vertex on the oracle's accepted tracks reproduces the oracle's
+    vertex decisions for frames without an overflow."""
+    import torch
+    cfg = dataclasses.replace(synth.CONFIGS[1], lam=1.0, noise_per_layer=1, signal_frac=0.6)
+    fs = synth.generate(cfg, n_frames=1500, salt=11)
+    p = default_params()
+    orc = oracle.run(fs, p)
+    k = orc.tracks[(orc.tracks[:, 6] == 1) & (orc.tracks[:, 7] == 0)]
+    F = fs.n_frames
+    off = np.searchsorted(k[:, 0], np.arange(F + 1)).astype(np.int32)
+    hits = k[:, 1:5].astype(np.int32)
+    print(f"case: vertex n_tracks={len(hits)}", flush=True)
+    dh = lib.to_device(fs)
+    gf, gc, gv = lib.vertex(dh, torch.from_numpy(hits).cuda(), torch.from_numpy(off).cuda(), p)
+    gf, gc, gv = gf.cpu().numpy(), gc.cpu().numpy(), gv.cpu().numpy()
+    ok = (orc.amb == 0) & ((orc.flags & (2 | 4 | 32)) == 0)
+    assert ok.sum() > 1000
+    assert np.array_equal(gf[ok] & 24, orc.flags[ok] & 24)
+    assert np.array_equal(gc[ok], orc.counts[ok, 2])
+    v = ok & ((orc.flags & 16) != 0)
+    assert v.sum() > 100
+    assert np.allclose(gv[v, :3], orc.vertex[v, :3], rtol=1e-4, atol=1e-3)
+
+
+def test_deterministic_outputs(lib):
+    import torch
+    fs = synth.generate(2, n_frames=2000)
+    dh = lib.to_device(fs)
+    p = default_params()
+    a = lib.select_frames(dh, p)
+    b = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    fa, ca, va = a.result()
+    fb, cb, vb = b.result()
+    assert np.array_equal(fa, fb) and np.array_equal(ca, cb)
+    assert np.array_equal(np.nan_to_num(va), np.nan_to_num(vb))
+    ta, ka, kfa, _ = a.lists(fs.layer_offsets)
+    tb, kb, kfb, _ = b.lists(fs.layer_offsets)
+    assert sorted(map(tuple, ta.tolist())) == sorted(map(tuple, tb.tolist()))
+    assert sorted(map(tuple, ka.tolist())) == sorted(map(tuple, kb.tolist()))
+
+
+def test_full_nominal_sampled(lib):
+    """The benchmark workload (100,000 nominal frames, benchmark launch
+    configuration) compared with the oracle on 2,000 sampled frames."""
+    import torch
+    fs = synth.generate(2)
+    p = default_params()
+    print(f"case: full cfg2 {fs.n_frames} frames", flush=True)
+    dh = lib.to_device(fs)
+    sel = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    flags, counts, vtx = sel.result()
+    trips, tracks, kf, c = sel.lists(fs.layer_offsets)
+    assert c[2] == 0
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(fs.n_frames, 2000, replace=False))
+    # oracle on the picked frames, one sub-batch per frame (hit indices rebased)
+    sub_trips, sub_tracks, sub_kf = [], [], []
+    orcs = []
+    for i, f in enumerate(pick):
+        sub = fs.subset(int(f), int(f) + 1)
+        orcs.append(oracle.run(sub, p))
+        base = fs.layer_offsets[4 * f]
+        m = trips[:, 0] == f
+        t = trips[m].copy(); t[:, 0] = i; t[:, 1:] -= base
+        sub_trips.append(t)
+        m = tracks[:, 0] == f
+        k = tracks[m].copy(); k[:, 0] = i; k[:, 1:] -= base
+        sub_tracks.append(k)
+        sub_kf.append(kf[m])
+    # merge the per-frame oracle results into one result over len(pick) frames
+    orc = oracle.OracleResult(
+        np.concatenate([o.flags for o in orcs]), np.concatenate([o.amb for o in orcs]),
+        np.concatenate([o.counts for o in orcs]), np.concatenate([o.namb for o in orcs]),
+        np.concatenate([o.vertex for o in orcs]), sum(o.stats for o in orcs), 0.0)
+
+    def cat(name, idx_cols, rows_of):
+        out = []
+        for i, o in enumerate(orcs):
+            a = getattr(o, name).copy()
+            a[:, 0] = i
+            out.append(a)
+        return np.concatenate(out) if out else np.zeros((0, idx_cols))
+    orc.trips = cat("trips", 6, None)
+    orc.trip_rtc = np.concatenate([o.trip_rtc for o in orcs])
+    orc.tracks = cat("tracks", 8, None)
+    orc.track_f = np.concatenate([o.track_f for o in orcs])
+    orc.triples = cat("triples", 12, None)
+    bad, stats = compare(orc, flags, counts, vtx, np.concatenate(sub_trips), np.concatenate(sub_tracks),
+                         np.concatenate(sub_kf), frames=pick)
+    print("full cfg2 sampled", stats, flush=True)
+    assert_parity(bad, stats, "full cfg2 sampled")
+    # properties over all frames: counts non-negative, KEEP iff another bit
+    keep = (flags & 1) != 0
+    assert np.array_equal(keep, (flags & 62) != 0)
+    assert np.all(counts >= 0)
