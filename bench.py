@@ -2,9 +2,13 @@
 
 One step = the whole selection (Selection Cuts -> Track Reconstruction ->
 Vertex Fit) over one batch of synthetic frames already resident in HBM.
-Workload: the nominal-rate plain path, 100,000 frames of 64 ns at 1e8 mu/s
+Workload: the nominal rate, 100,000 frames of 64 ns at 1e8 mu/s
 (Poisson(6.4) Michel decays per frame, 5 noise hits per layer, signal in 1 %
-of frames).  Prints one JSON line.
+of frames).  Both forms run on it: the plain per-frame kernels and the
+batched persistent form (one hipGraph launch, autotuned shape); `value` is
+the batched form.  Optional legs: the mixed-rate 1,000,000-frame batch
+(both forms, identical outputs required) and the alignment gradient.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,8 +26,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 STAGES = ("cuts", "tracks", "vertex_prep", "vertex")
-KERNELS = {"cuts": "k_cuts", "tracks": "k_tracks", "vertex_prep": "k_vcand+k_vprep_list",
-           "vertex": "k_vframes_list"}
 
 # Algorithmic float32 operations of the track stage per selected triplet
 # (first fit, layer-3 crossing, second fit, weighted combination), plus 8 per
@@ -31,9 +33,16 @@ KERNELS = {"cuts": "k_cuts", "tracks": "k_tracks", "vertex_prep": "k_vcand+k_vpr
 # circumcircle, the linearised triplet fit and the circle intersection.
 FLOPS_PER_TRIPLET = 430
 FLOPS_PER_L3_HIT = 8
+# Selection Cuts: cos Phi of a pair (2 mul, 1 add, 1 scale) = 4, plus the
+# slope tan(lambda) of an (h1, h2) pair (sub, mul) = 2; per joined
+# combination the (h0, h1) slope and the difference = 3; per Delta-lambda
+# survivor the signed circumradius test (3 chord differences, cross product,
+# 3 squared chords, their product, 4 cross^2, two scaled bounds) = 24.
+FLOPS_PAIR01, FLOPS_PAIR12, FLOPS_JOIN, FLOPS_RTC = 4, 6, 3, 24
 
-# HBM traffic of k_tracks on this workload from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE, keyed by the hash of the kernel source it was measured on.
+# HBM traffic of the roofline kernel on this workload from rocprofv3
+# FETCH_SIZE / WRITE_SIZE, keyed by the hash of the kernel source it was
+# measured on (null once the source changes).
 TRAFFIC = {}
 
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X float32 vector (published)
@@ -41,7 +50,8 @@ PEAK_FP32 = 157.3   # TFLOP/s, MI355X float32 vector (published)
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for p in ("paper_2206_11535_amd/csrc/mu3e.hip", "paper_2206_11535_amd/csrc/mu3e_math.hpp"):
+    for p in ("paper_2206_11535_amd/csrc/mu3e.hip", "paper_2206_11535_amd/csrc/mu3e_math.hpp",
+              "paper_2206_11535_amd/csrc/mu3e_adjoint.hpp"):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -53,9 +63,9 @@ class Hip:
     def __init__(self):
         self.L = ctypes.CDLL("libamdhip64.so.7")
         self.L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.L.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         self.L.hipEventSynchronize.argtypes = [ctypes.c_void_p]
-        self.L.hipEventDestroy.argtypes = [ctypes.c_void_p]
 
     def events(self, n):
         arr = (ctypes.c_void_p * n)()
@@ -64,6 +74,9 @@ class Hip:
             assert self.L.hipEventCreate(ctypes.byref(e)) == 0
             arr[i] = e
         return arr
+
+    def record(self, e, stream):
+        assert self.L.hipEventRecord(e, ctypes.c_void_p(stream.cuda_stream)) == 0
 
     def elapsed(self, a, b) -> float:
         ms = ctypes.c_float()
@@ -82,8 +95,106 @@ def cpu_baseline(fs, params, min_seconds=10.0):
         done += fs.n_frames
         reps += 1
     return {"value": done / secs, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"the {fs.n_frames}-frame workload x {reps} passes ({secs:.1f} s, FP64 C++ oracle, "
-                      f"OpenMP over frames)"}
+            "sample": f"the {fs.n_frames}-frame nominal workload x {reps} passes ({secs:.1f} s of the FP64 C++ "
+                      f"oracle, OpenMP over frames)"}
+
+
+def time_steps(sel, dh, stream, hip, steps, warmup, staged=False):
+    """Mean ms per step over `steps` timed steps (HIP events on the launch
+    stream, bracketed by device synchronisation); per-stage means if the
+    selector records stage events."""
+    import torch
+    for _ in range(warmup):
+        sel.run(dh, stream)
+    torch.cuda.synchronize()
+    c = sel.counters()
+    if c[2] != 0:
+        raise RuntimeError(f"candidate lists overflowed the workspace: {c}")
+    ev = [hip.events(5) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if staged:
+            sel.run(dh, stream, events=ev[k])
+        else:
+            hip.record(ev[k][0], stream)
+            sel.run(dh, stream)
+            hip.record(ev[k][4], stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [hip.elapsed(ev[k][0], ev[k][4]) for k in range(steps)]
+    stage = None
+    if staged:
+        stage = np.mean([[hip.elapsed(ev[k][s], ev[k][s + 1]) for s in range(4)] for k in range(steps)], axis=0)
+    return float(np.mean(step_ms)), stage, wall
+
+
+def fitted_triplets(sel, fs):
+    from paper_2206_11535_amd import lib
+    flags, counts, _ = sel.result()
+    ovf = (flags & (lib.TRIPLET_OVF | lib.HITS_OVF)) != 0
+    n3 = np.diff(fs.layer_offsets)[3::4]
+    fitted = int(counts[~ovf, 0].sum())
+    flops = float(np.sum(counts[~ovf, 0].astype(np.float64) * (FLOPS_PER_TRIPLET + FLOPS_PER_L3_HIT * n3[~ovf])))
+    return fitted, flops, flags
+
+
+def _pairs(fs, la, lb):
+    """Global hit indices of every (layer la, layer lb) pair of each frame."""
+    lo = fs.layer_offsets.astype(np.int64)
+    oa, ob = lo[la:-1:4], lo[lb:-1:4]
+    na, nb = lo[la + 1::4] - oa, lo[lb + 1::4] - ob
+    npair = na * nb
+    start = np.concatenate([[0], np.cumsum(npair)[:-1]])
+    pf = np.repeat(np.arange(len(na)), npair)
+    k = np.arange(int(npair.sum()), dtype=np.int64) - start[pf]
+    return oa[pf] + k // nb[pf], ob[pf] + k % nb[pf]
+
+
+def cut_work(fs, p):
+    """Counts of the units the Selection Cuts work on, from the hits on the
+    host in float32 (the same windows): pairs per layer pair, joined
+    combinations and Delta-lambda survivors.  Work accounting only."""
+    x, y, z = fs.x, fs.y, fs.z
+    R = np.asarray(p["r_layer"], np.float32)
+    i0, i1 = _pairs(fs, 0, 1)
+    j1, j2 = _pairs(fs, 1, 2)
+    c01 = (x[i0] * x[i1] + y[i0] * y[i1]) * np.float32(1.0 / (R[0] * R[1]))
+    c12 = (x[j1] * x[j2] + y[j1] * y[j2]) * np.float32(1.0 / (R[1] * R[2]))
+    a = (c01 >= p["cosphi01"][0]) & (c01 <= p["cosphi01"][1])
+    b = (c12 >= p["cosphi12"][0]) & (c12 <= p["cosphi12"][1])
+    i0, i1, j1, j2 = i0[a], i1[a], j1[b], j2[b]
+    t01 = (z[i1] - z[i0]) * np.float32(1.0 / (R[1] - R[0]))
+    t12 = (z[j2] - z[j1]) * np.float32(1.0 / (R[2] - R[1]))
+    # join on the shared layer-1 hit
+    o01, o12 = np.argsort(i1, kind="stable"), np.argsort(j1, kind="stable")
+    i1s, t01s = i1[o01], t01[o01]
+    j1s, t12s = j1[o12], t12[o12]
+    n = fs.n_hits
+    n01 = np.bincount(i1s, minlength=n)
+    n12 = np.bincount(j1s, minlength=n)
+    s12 = np.concatenate([[0], np.cumsum(n12)[:-1]])
+    rep = n12[i1s]
+    joins = int(rep.sum())
+    left = np.repeat(np.arange(len(i1s)), rep)
+    st = np.concatenate([[0], np.cumsum(rep)[:-1]])
+    right = s12[i1s[left]] + (np.arange(joins) - st[left])
+    dl = t12s[right] - t01s[left]
+    dl_pass = int(np.count_nonzero((dl >= p["dlambda"][0]) & (dl <= p["dlambda"][1])))
+    del n01
+    return {"pairs01": int(a.size), "pairs12": int(b.size), "joins": joins, "dlambda_pass": dl_pass}
+
+
+def cut_flops(w) -> float:
+    return float(FLOPS_PAIR01 * w["pairs01"] + FLOPS_PAIR12 * w["pairs12"] + FLOPS_JOIN * w["joins"] +
+                 FLOPS_RTC * w["dlambda_pass"])
+
+
+def same_outputs(a, b) -> bool:
+    fa, ca, va = a.result()
+    fb, cb, vb = b.result()
+    return bool(np.array_equal(fa, fb) and np.array_equal(ca, cb) and
+                np.array_equal(np.nan_to_num(va), np.nan_to_num(vb)))
 
 
 def main():
@@ -93,79 +204,119 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=None, help="prefix of the workload (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed", action="store_true", help="also the mixed-rate 1,000,000-frame batch")
+    ap.add_argument("--align", action="store_true", help="also the alignment gradient (misaligned frames)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the HBM traffic counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {a.gpus} requested); frames are independent and the "
-              f"multi-GPU form is a static frame split, not built here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {a.gpus} requested): frames are independent, so more GPUs "
+              f"would each take a contiguous range of frames; that split is not built here", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_2206_11535_amd import lib, synth
+    from paper_2206_11535_amd import autotune, lib, synth
     from paper_2206_11535_amd.params import default_params
 
-    cfg = synth.CONFIGS[2]
-    fs = synth.generate(cfg, n_frames=a.frames)
+    fs = synth.generate(synth.CONFIGS[2], n_frames=a.frames)
     p = default_params()
     F = fs.n_frames
     dev = torch.device("cuda:0")
     dh = lib.to_device(fs, dev)
-    sel = lib.Selector(F, p, device=dev)
     hip = Hip()
     stream = torch.cuda.current_stream(dev)
-    ev = [hip.events(5) for _ in range(a.steps)]
-    for _ in range(a.warmup):
-        sel.run(dh, stream)
-    torch.cuda.synchronize()
-    c = sel.counters()
-    if c[2] != 0:
-        raise RuntimeError(f"candidate lists overflowed the workspace: {c}")
-    t0 = time.perf_counter()
+    # ---- plain form (per-stage events)
+    plain = lib.Selector(F, p, device=dev)
+    ms_plain, stage_ms, _ = time_steps(plain, dh, stream, hip, a.steps, a.warmup, staged=True)
+    fitted, flops, flags = fitted_triplets(plain, fs)
+    # ---- batched form (autotuned shape, cached)
+    (w, c), _, _ = autotune.tune(dh, p)
+    batched = lib.BatchedSelector(dh, p, device=dev, waves_per_cu=w, frames_per_claim=c)
+    ms_batched, _, wall = time_steps(batched, dh, stream, hip, a.steps, a.warmup)
+    identical = same_outputs(plain, batched)
+    # the persistent kernel alone: the same sequence launched eagerly with
+    # events around it on the launch stream
+    ev = [hip.events(3) for _ in range(a.steps)]
     for k in range(a.steps):
-        sel.run(dh, stream, events=ev[k])
+        batched.run(None, stream, events=ev[k])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stage_ms = np.zeros(4)
-    step_ms = []
-    for k in range(a.steps):
-        for s in range(4):
-            stage_ms[s] += hip.elapsed(ev[k][s], ev[k][s + 1])
-        step_ms.append(hip.elapsed(ev[k][0], ev[k][4]))
-    stage_ms /= a.steps
+    ms_kbatched = float(np.mean([hip.elapsed(e[0], e[1]) for e in ev]))
+    identical = identical and same_outputs(plain, batched)
+    work = cut_work(fs, p)
+    kb_flops = cut_flops(work) + flops
     if a.copy_probe:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)   # an elementwise kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
-    ms = float(np.mean(step_ms))
-    flags, counts, _ = sel.result()
-    ovf = (flags & (lib.TRIPLET_OVF | lib.HITS_OVF)) != 0
-    n3 = np.diff(fs.layer_offsets)[3::4]
-    fitted = int(counts[~ovf, 0].sum())
-    value = F / (ms / 1e3)
-    # roofline of the track kernel (algorithmic flops / its measured time)
-    flops = float(np.sum(counts[~ovf, 0].astype(np.float64) * (FLOPS_PER_TRIPLET + FLOPS_PER_L3_HIT * n3[~ovf])))
-    t_tracks = stage_ms[1] / 1e3
-    achieved = flops / t_tracks / 1e12
+    # roofline of the dominant kernel, the persistent cuts + fits kernel
+    # (algorithmic flops / its measured time)
+    achieved = kb_flops / (ms_kbatched / 1e3) / 1e12
+    tracks_achieved = flops / (stage_ms[1] / 1e3) / 1e12
     sh = source_hash()
     out = {
-        "metric": "frames/s at 1e8 mu/s-equivalent load (plain per-frame form)",
-        "value": value, "unit": "frames/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": "frames/s at 1e8 mu/s-equivalent load (batched persistent form; plain form alongside)",
+        "value": F / (ms_batched / 1e3), "unit": "frames/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_batched, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"nominal rate, {F} frames of 64 ns, Poisson(6.4) Michel decays + 5 noise "
-                               f"hits/layer, signal in 1% of frames", "frames": F, "form": "plain"},
-        "fitted_triplets_per_s": fitted / (ms / 1e3),
-        "stage_ms": {s: float(v) for s, v in zip(STAGES, stage_ms)},
+                               f"hits/layer, signal in 1% of frames", "frames": F, "form": "batched",
+                   "waves_per_cu": batched.effective[0], "frames_per_claim": batched.effective[1]},
+        "fitted_triplets_per_s": fitted / (ms_batched / 1e3),
+        "plain": {"value": F / (ms_plain / 1e3), "ms_per_step": ms_plain,
+                  "fitted_triplets_per_s": fitted / (ms_plain / 1e3),
+                  "stage_ms": {s: float(v) for s, v in zip(STAGES, stage_ms)},
+                  "k_tracks_tflops": tracks_achieved},
+        "batched_equals_plain": identical,
         "kept_fraction": float(np.mean(flags & lib.KEEP)),
-        "roofline": {"kernel": KERNELS["tracks"], "bound": "alu", "achieved": achieved, "peak": PEAK_FP32,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": TRAFFIC.get(sh), "flops_per_launch": flops, "source": sh},
+        "roofline": {"kernel": "k_batched", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": TRAFFIC.get(sh),
+                     "kernel_ms": ms_kbatched, "flops_per_launch": kb_flops, "work": work,
+                     "fitted_triplets": fitted, "source": sh},
         "wall_s_timed": wall,
         "paper_context": "1.4e6 frames/s on a GTX 1080Ti at 1e8 mu/s (Geant4 frames, not this workload)",
     }
+    if a.mixed:
+        fm = synth.generate(synth.CONFIGS[3])
+        dm = lib.to_device(fm, dev)
+        sp = lib.Selector(fm.n_frames, p, device=dev)
+        msp, _, _ = time_steps(sp, dm, stream, hip, max(3, a.steps // 4), 1)
+        (wm, cm), _, _ = autotune.tune(dm, p)
+        sb = lib.BatchedSelector(dm, p, device=dev, waves_per_cu=wm, frames_per_claim=cm)
+        msb, _, _ = time_steps(sb, dm, stream, hip, max(3, a.steps // 4), 1)
+        out["mixed"] = {"workload": f"{fm.n_frames} frames, lambda per frame from {{2, 6.4, 12, 20}}",
+                        "plain_frames_per_s": fm.n_frames / (msp / 1e3),
+                        "batched_frames_per_s": fm.n_frames / (msb / 1e3),
+                        "batched_equals_plain": same_outputs(sp, sb),
+                        "waves_per_cu": sb.effective[0], "frames_per_claim": sb.effective[1]}
+        del sp, sb, dm
+    if a.align:
+        fa = synth.generate(synth.CONFIGS[5])
+        da = lib.to_device(fa, dev)
+        sa = lib.Selector(fa.n_frames, p, device=dev)
+        sa.run(da, stream)
+        torch.cuda.synchronize()
+        _, tracks, _, _ = sa.lists(fa.layer_offsets)
+        trip = np.concatenate([tracks[:, [1, 2, 3]], tracks[:, [2, 3, 4]]]).astype(np.int32)
+        tt = torch.from_numpy(trip).to(dev)
+        theta = torch.zeros((synth.N_SENSORS, 4), dtype=torch.float32, device=dev)
+        gch = torch.ones(len(trip), dtype=torch.float32, device=dev)
+        for _ in range(2):
+            lib.align_backward(da, tt, theta, p, gch)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        for _ in range(a.steps):
+            lib.align_chi2(da, tt, theta, p)
+        e1.record()
+        for _ in range(a.steps):
+            lib.align_backward(da, tt, theta, p, gch)
+        e2.record()
+        e2.synchronize()
+        out["align"] = {"workload": f"{fa.n_frames} misaligned frames, {len(trip)} frozen triplets, "
+                                    f"{synth.N_SENSORS} sensors x 4 parameters",
+                        "forward_ms": e0.elapsed_time(e1) / a.steps, "backward_ms": e1.elapsed_time(e2) / a.steps}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fs, p)
     print(json.dumps(out), flush=True)

@@ -101,17 +101,26 @@ typedef struct {
 } mu3e_params_t;
 
 /* Optional debug view, filled on return of mu3e_select_frames (host struct
- * holding device pointers into the caller's workspace).  After the stream is
+ * holding device pointers into the caller's workspace).  The triplet list
+ * is handed out to the waves of the cuts kernel in chunks (one atomic per
+ * chunk); a frame's triplets may span chunks.  After the stream is
  * synchronised:
- *   counters[0]  triplets appended to the triplet list (true count, may
- *                exceed triplet_capacity)
- *   counters[1]  tracks appended to the track list (true count)
- *   counters[2]  status bits: 1 triplet list full, 2 track list full,
- *                4 a frame's layer_offsets were malformed (decreasing,
+ *   counters[0]  triplets selected in total (true count)
+ *   counters[1]  tracks appended to the track list (true count, may exceed
+ *                track_capacity)
+ *   counters[2]  status bits: 1 the triplet list was full, 2 track list
+ *                full, 4 a frame's layer_offsets were malformed (decreasing,
  *                negative or beyond n_hits; that frame was skipped)
- *   triplets     [triplet_capacity][2]: frame, packed frame-local indices
- *                i0 | i1 << 8 | i2 << 16 (hit = layer_offsets[4f+l] + il)
- *   tracks       [track_capacity][8]: frame, hit0, hit1, hit2, hit3, next,
+ *   counters[7]  triplet entries handed out in chunks of a fixed size
+ *                (also past the capacity)
+ *   chunks       [max_chunks][4]: start, count, fitted, 0 -- chunk c holds
+ *                triplet entries [start, start + count); the rows in use are
+ *                those with start + chunk size <= triplet_capacity, i.e. the
+ *                first min(counters[7], triplet_capacity) / chunk size rows,
+ *                and chunk c starts at c * chunk size
+ *   triplets     [triplet_capacity][2]: frame, packed frame-local
+ *                indices i0 | i1 << 8 | i2 << 16 (hit = layer_offsets[4f+l] + il)
+ *   tracks       [track_capacity][8]: frame, hit0, hit1, hit2, hit3, 0,
  *                float bits of kappa_bar, float bits of chi2_global
  * Triplets of frames flagged MU3E_TRIPLET_OVF may appear in the list; they
  * are never fitted. */
@@ -120,15 +129,20 @@ typedef struct {
   const int32_t *triplets;
   const int32_t *tracks;
   int32_t triplet_capacity, track_capacity;
+  const int32_t *chunks;
+  int32_t max_chunks, chunk_size;
 } mu3e_debug_t;
 
 const char *mu3e_status_string(mu3e_status s);
 
 /* Workspace bytes for mu3e_select_frames over n_frames frames with room for
- * triplet_capacity selected triplets and track_capacity tracks in total.  A
- * run whose lists fill up reports it in counters[2] (mu3e_debug_t); its
- * outputs are then incomplete and the call should be repeated with the
- * true counts from counters[0..1].  Returns 0 for invalid sizes. */
+ * triplet_capacity (<= 2^30) selected triplets and track_capacity tracks in
+ * total.  The triplet list is shared by all waves in chunks of
+ * triplet_capacity / (2 * waves) entries (clamped to [64, 4096]), so allow
+ * about twice the expected number of selected triplets; a run whose lists
+ * fill up reports it in counters[2] (mu3e_debug_t); its outputs are then
+ * incomplete and the call should be repeated with larger capacities.
+ * Returns 0 for invalid sizes. */
 size_t mu3e_select_workspace_size(int32_t n_frames, int32_t triplet_capacity,
                                   int32_t track_capacity);
 
@@ -191,6 +205,47 @@ mu3e_status mu3e_vertex(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
                         const mu3e_params_t *params, uint32_t *frame_flags,
                         int32_t *frame_combos, float *frame_vertex, void *workspace,
                         size_t workspace_bytes, hipStream_t stream);
+
+/* ---- Batched form ------------------------------------------------------
+ * A plan captures the whole selection of one batch of frames into a HIP
+ * graph around one persistent kernel: waves claim chunks of frames from a
+ * shared counter (work stealing over uneven frames), run the Selection Cuts
+ * of each frame and fit the pending survivors of all their frames 64 at a
+ * time; the float64 re-evaluation and the vertex stage follow in the same
+ * graph.  Outputs are identical to mu3e_select_frames.  The plan binds the
+ * hit, output and workspace buffers given here: refill them and call
+ * mu3e_plan_run again.  Runs of one plan (or of plans sharing a workspace)
+ * must not overlap. */
+typedef struct mu3e_plan mu3e_plan_t;
+
+typedef struct {
+  int32_t waves_per_cu;       /* persistent waves per compute unit (0: default 12;
+                                 capped by occupancy)                           */
+  int32_t frames_per_claim;   /* frames taken per work-stealing claim (0: 4)   */
+} mu3e_tuning_t;
+
+/* Workspace as mu3e_select_workspace_size.  tuning may be NULL.  Allocates
+ * the plan object and the graph (host and driver memory). */
+mu3e_status mu3e_plan_create(mu3e_plan_t **plan, const mu3e_hits_t *hits,
+                             const mu3e_params_t *params, uint32_t *frame_flags,
+                             int32_t *frame_counts, float *frame_vertex, void *workspace,
+                             size_t workspace_bytes, int32_t triplet_capacity,
+                             int32_t track_capacity, const mu3e_tuning_t *tuning);
+
+/* One graph launch on the stream (asynchronous; no allocation). */
+mu3e_status mu3e_plan_run(mu3e_plan_t *plan, hipStream_t stream);
+
+/* The same kernel sequence as mu3e_plan_run, launched directly on the stream
+ * (no graph) with events[0..2] (caller-created, timing enabled) recorded
+ * before and after the persistent kernel and after the last kernel, so its
+ * duration can be measured on the stream it runs on.  Identical outputs. */
+mu3e_status mu3e_plan_run_timed(mu3e_plan_t *plan, hipStream_t stream, hipEvent_t *events);
+
+/* The plan's debug view (as mu3e_select_frames fills it) and the tuning in
+ * effect; either pointer may be NULL. */
+mu3e_status mu3e_plan_info(const mu3e_plan_t *plan, mu3e_debug_t *dbg, mu3e_tuning_t *tuning);
+
+void mu3e_plan_destroy(mu3e_plan_t *plan);
 
 /* ---- Alignment (differentiable form) ---------------------------------
  * theta[n_sensors][4] = (tx, ty, tz, alpha) per sensor: a hit h on sensor s

@@ -1,0 +1,81 @@
+"""Autotuner of the batched form: persistent waves per compute unit and
+frames per work-stealing claim.
+
+Each candidate plan runs the given workload (already resident on the GPU);
+its mean step time over HIP-event-timed repeats is measured and the fastest
+shape is cached in tuning_cache.json, keyed by GPU architecture, ROCm
+version and workload class (frames and mean hits per frame, rounded).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(PKG, "tuning_cache.json")
+
+WAVES_PER_CU = (4, 6, 8, 12, 16, 20)
+FRAMES_PER_CLAIM = (1, 2, 4, 8, 16, 32)
+
+
+def workload_key(hits, arch: str) -> str:
+    import torch
+    hpf = hits.n_hits / max(hits.n_frames, 1)
+    return f"{arch}|rocm{torch.version.hip}|F{hits.n_frames}|hpf{round(hpf / 4) * 4}"
+
+
+def load_cache() -> dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def time_plan(sel, reps: int = 5, warmup: int = 2) -> float:
+    import torch
+    for _ in range(warmup):
+        sel.run()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        sel.run()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: int = 5,
+         candidates=None, use_cache: bool = True, verbose: bool = False):
+    """Return ((waves_per_cu, frames_per_claim), ms, table)."""
+    import torch
+    from . import lib
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = workload_key(hits, arch)
+    cache = load_cache()
+    if use_cache and key in cache:
+        e = cache[key]
+        return (e["waves_per_cu"], e["frames_per_claim"]), e["ms"], None
+    cand = candidates or [(w, c) for w in WAVES_PER_CU for c in FRAMES_PER_CLAIM]
+    table = []
+    seen = set()
+    for w, c in cand:
+        sel = lib.BatchedSelector(hits, params, triplet_capacity, track_capacity, waves_per_cu=w,
+                                  frames_per_claim=c)
+        if sel.effective in seen:          # capped by occupancy: same shape as before
+            del sel
+            continue
+        seen.add(sel.effective)
+        ms = time_plan(sel, reps)
+        table.append((sel.effective[0], sel.effective[1], ms))
+        if verbose:
+            print(f"  waves/CU {sel.effective[0]:3d} frames/claim {sel.effective[1]:3d}: {ms:.4f} ms", flush=True)
+        del sel
+    best = min(table, key=lambda r: r[2])
+    cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "ms": best[2]}
+    with open(CACHE, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    return (best[0], best[1]), best[2], table

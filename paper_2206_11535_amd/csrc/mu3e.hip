@@ -28,17 +28,82 @@
 #include <math.h>
 #include <string.h>
 
+#include <new>
+
 using namespace mu3e;
 
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kTripBuf = 1024;               // LDS triplet buffer per frame
-constexpr int kStreamAbove = kTripBuf - 64;  // larger caps: stream survivors out
 constexpr int kCounters = 64;                // int32 counters at the workspace head
+constexpr int kMinChunk = 64;                // triplet-list chunk sizes lie in [64, 4096]
+constexpr int kMaxChunk = 4096;
+constexpr int kMaxTripletCapacity = 1 << 30; // keeps the chunk bump counter within int32
 
-// counters: [0] triplets appended, [1] tracks appended, [2] status bits
+// counters: [0] triplets selected, [1] tracks appended, [2] status bits,
+// [3] candidate frames of the vertex stage, [4] their track-table size,
+// [5] track candidates re-evaluated in float64, [6] frame claim counter of
+// the batched form, [7] triplet-list entries handed out in chunks (also
+// past the capacity: each grant adds one chunk)
 enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
+
+// ----------------------------------------------------------- triplet list
+// Selected triplets are appended to chunks of one list: a wave takes a chunk
+// from a bump counter (one atomic per chunk) and fills it with ballot
+// compaction; when a wave's survivors do not fit, it closes the chunk and
+// takes the next, so a frame may span chunks.  Chunk table row c holds
+// [start, count, fitted, 0]; entries [fitted, count) of a chunk are fitted by
+// k_tracks (the batched form fits the rest itself).
+struct TripList {
+  int32_t* trips;    // [capacity][2]: frame, packed frame-local i0 | i1 << 8 | i2 << 16
+  int32_t* chunks;   // [capacity / kMinChunk + 1][4]
+  int capacity, chunk;
+};
+
+// A wave's current chunk; wave-uniform.  cap == 0: no chunk held.
+struct Cursor {
+  int start, cap, used, id;
+  bool full;   // the list ran out: stop asking
+};
+
+__device__ inline Cursor cursor_init() { return Cursor{0, 0, 0, -1, false}; }
+
+__device__ inline void cursor_close(const Cursor& c, int fitted, const TripList& T) {
+  if (c.cap > 0 && threadIdx.x == 0) {
+    T.chunks[4 * c.id + 1] = c.used;
+    T.chunks[4 * c.id + 2] = fitted;
+  }
+}
+
+// All chunks of a launch have the same size, so the k-th grant starts at
+// k * chunk and the granted chunks (those ending within capacity) are rows
+// 0 .. min(counters[7], capacity) / chunk - 1 of the table.
+__device__ inline int chunks_granted(const TripList& T, const int32_t* __restrict__ counters) {
+  const int handed = counters[7] < T.capacity ? counters[7] : T.capacity;
+  return handed / T.chunk;
+}
+
+__device__ inline void cursor_open(Cursor& c, const TripList& T, int32_t* __restrict__ counters) {
+  int start = -1, id = -1;
+  if (threadIdx.x == 0) {
+    const int s0 = atomicAdd(&counters[7], T.chunk);
+    if (s0 <= T.capacity - T.chunk) {
+      id = s0 / T.chunk;
+      int32_t* row = T.chunks + 4 * id;
+      row[0] = s0; row[1] = 0; row[2] = 0; row[3] = 0;
+      start = s0;
+    } else {
+      atomicOr(&counters[2], ST_TRIP_FULL);
+    }
+  }
+  start = __shfl(start, 0, 64);
+  id = __shfl(id, 0, 64);
+  c.start = start < 0 ? 0 : start;
+  c.cap = start < 0 ? 0 : T.chunk;
+  c.used = 0;
+  c.id = id;
+  c.full = start < 0;
+}
 
 __device__ inline uint64_t lanemask_lt() {
   const unsigned lane = threadIdx.x & 63u;
@@ -102,85 +167,77 @@ __device__ inline bool rtc_cut(float x0, float y0, float x1, float y1, float x2,
 }
 
 // =================================================================== k_cuts
-__global__ void __launch_bounds__(64)
-k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
-       const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
-       int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ head,
-       int32_t* __restrict__ ccnt, int32_t* __restrict__ trips, int trip_cap,
-       int32_t* __restrict__ counters) {
-  __shared__ float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
-  __shared__ unsigned long long sm01[2 * kMaxLayerHits];
-  __shared__ uint32_t spend[2 * kWave];
-  __shared__ uint32_t stb[kTripBuf];
+struct CutLds {
+  float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
+  unsigned long long sm01[2 * kMaxLayerHits];
+  uint32_t spend[2 * kWave];
+};
+
+// Selection Cuts of frame f by one wave (Alg. 2): the frame's layer-0..2
+// hits are staged in LDS; a 128-bit mask of layer-0 partners passing Phi01
+// per layer-1 hit; (h1, h2) pairs passing Phi12 are streamed through an LDS
+// queue and each full wave of pairs is joined against its Phi01 partners
+// (Delta lambda, then r_tc).  Survivors are ballot-compacted into the
+// wave's chunks of the triplet list (cur; done = the wave's fitted prefix of
+// its current chunk, recorded when the chunk is closed); returns the number
+// committed (0 when the frame overflows max_triplets) and writes the frame's
+// flags and counts.
+__device__ int cut_frame(int f, const float* __restrict__ X, const float* __restrict__ Y,
+                         const float* __restrict__ Z, const int32_t* __restrict__ lo, int n_hits, const Consts& C,
+                         CutLds& L, const TripList& T, Cursor& cur, int& done,
+                         uint32_t* __restrict__ flags, int32_t* __restrict__ counts, float* __restrict__ vtx,
+                         int32_t* __restrict__ ccnt, int32_t* __restrict__ counters) {
   const int lane = threadIdx.x;
-  const bool stream = C.max_trip > kStreamAbove;
-
-  for (int f = blockIdx.x; f < F; f += gridDim.x) {
-    const int b0 = lo[4 * f], b1 = lo[4 * f + 1], b2 = lo[4 * f + 2], b3 = lo[4 * f + 3], b4 = lo[4 * f + 4];
-    const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2, n3 = b4 - b3;
-    if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
-    if (lane == 0) { head[f] = -1; ccnt[f] = 0; counts[3 * f + 1] = 0; counts[3 * f + 2] = 0; }
-    if (b0 < 0 || n0 < 0 || n1 < 0 || n2 < 0 || n3 < 0 || b4 > n_hits) {
-      // malformed offsets: nothing of this frame is read
-      if (lane == 0) { flags[f] = 0; counts[3 * f] = 0; atomicOr(&counters[2], ST_BAD_OFFSETS); }
-      continue;
-    }
-    if (n0 > C.max_lh || n1 > C.max_lh || n2 > C.max_lh || n3 > C.max_lh) {
-      if (lane == 0) { flags[f] = MU3E_HITS_OVF | MU3E_KEEP; counts[3 * f] = 0; }
-      continue;
-    }
-    // ---- stage the layer-0..2 hits of the frame (coalesced)
-    const int n012 = n0 + n1 + n2;
-    for (int i = lane; i < n012; i += kWave) {
-      const int l = (i >= n0) + (i >= n0 + n1);
-      const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
-      sx[l * kMaxLayerHits + k] = X[b0 + i];
-      sy[l * kMaxLayerHits + k] = Y[b0 + i];
-      sz[l * kMaxLayerHits + k] = Z[b0 + i];
+  const int b0 = lo[4 * f], b1 = lo[4 * f + 1], b2 = lo[4 * f + 2], b3 = lo[4 * f + 3], b4 = lo[4 * f + 4];
+  const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2, n3 = b4 - b3;
+  if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
+  if (lane == 0) { ccnt[f] = 0; counts[3 * f + 1] = 0; counts[3 * f + 2] = 0; }
+  if (b0 < 0 || n0 < 0 || n1 < 0 || n2 < 0 || n3 < 0 || b4 > n_hits) {
+    // malformed offsets: nothing of this frame is read
+    if (lane == 0) { flags[f] = 0; counts[3 * f] = 0; atomicOr(&counters[2], ST_BAD_OFFSETS); }
+    return 0;
+  }
+  if (n0 > C.max_lh || n1 > C.max_lh || n2 > C.max_lh || n3 > C.max_lh) {
+    if (lane == 0) { flags[f] = MU3E_HITS_OVF | MU3E_KEEP; counts[3 * f] = 0; }
+    return 0;
+  }
+  // ---- stage the layer-0..2 hits of the frame (coalesced), clear the masks
+  const int n012 = n0 + n1 + n2;
+  for (int i = lane; i < n012; i += kWave) {
+    const int l = (i >= n0) + (i >= n0 + n1);
+    const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
+    L.sx[l * kMaxLayerHits + k] = X[b0 + i];
+    L.sy[l * kMaxLayerHits + k] = Y[b0 + i];
+    L.sz[l * kMaxLayerHits + k] = Z[b0 + i];
+  }
+  for (int i = lane; i < 2 * n1; i += kWave) L.sm01[i] = 0ull;
+  __syncthreads();
+  int total = 0;   // triplets passing all cuts (exact)
+  const int fid = cur.id, fused = cur.used;   // where this frame's entries begin
+  if (n0 > 0 && n2 > 0) {
+    // ---- Phi01 over all (i0, i1) pairs
+    const int n01 = n0 * n1;
+    const float r0 = 1.0f / (float)n0;
+    for (int p = lane; p < n01; p += kWave) {
+      const int i1 = (int)(((float)p + 0.5f) * r0);   // exact for p < 2^14
+      const int i0 = p - i1 * n0;
+      if (cos_cut(L.sx[i0], L.sy[i0], L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], C.invRR01, C.c01_lo,
+                  C.c01_hi, C.R[0], C.R[1]))
+        atomicOr(&L.sm01[2 * i1 + (i0 >> 6)], 1ull << (i0 & 63));
     }
     __syncthreads();
-    // ---- layer-0 partners of every layer-1 hit (Phi01 window)
-    for (int i1 = lane; i1 < n1; i1 += kWave) {
-      const float x1 = sx[kMaxLayerHits + i1], y1 = sy[kMaxLayerHits + i1];
-      unsigned long long w0 = 0, w1 = 0;
-      for (int i0 = 0; i0 < n0; ++i0) {
-        const bool p = cos_cut(sx[i0], sy[i0], x1, y1, C.invRR01, C.c01_lo, C.c01_hi, C.R[0], C.R[1]);
-        if (p) { if (i0 < 64) w0 |= 1ull << i0; else w1 |= 1ull << (i0 - 64); }
-      }
-      sm01[2 * i1] = w0;
-      sm01[2 * i1 + 1] = w1;
-    }
-    __syncthreads();
-
-    int total = 0;   // triplets passing all cuts (exact)
-    int fill = 0;    // entries in the LDS buffer
-    auto flush = [&]() {
-      if (fill == 0) return;
-      int base = 0;
-      if (lane == 0) base = atomicAdd(&counters[0], fill);
-      base = __shfl(base, 0, 64);
-      for (int j = lane; j < fill; j += kWave) {
-        const int g = base + j;
-        if (g < trip_cap) { trips[2 * g] = f; trips[2 * g + 1] = (int32_t)stb[j]; }
-      }
-      if (lane == 0 && base + fill > trip_cap) atomicOr(&counters[2], ST_TRIP_FULL);
-      fill = 0;
-      __syncthreads();
-    };
-    // join k pending (h1, h2) pairs, lane j taking pair j, against the
-    // layer-0 partners of its h1
     auto join = [&](int k) {
       const bool have = lane < k;
-      const uint32_t e = have ? spend[lane] : 0u;
+      const uint32_t e = have ? L.spend[lane] : 0u;
       const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
-      const float x1 = sx[kMaxLayerHits + i1], y1 = sy[kMaxLayerHits + i1], z1 = sz[kMaxLayerHits + i1];
-      const float x2 = sx[2 * kMaxLayerHits + i2], y2 = sy[2 * kMaxLayerHits + i2], z2 = sz[2 * kMaxLayerHits + i2];
+      const float x1 = L.sx[kMaxLayerHits + i1], y1 = L.sy[kMaxLayerHits + i1], z1 = L.sz[kMaxLayerHits + i1];
+      const float x2 = L.sx[2 * kMaxLayerHits + i2], y2 = L.sy[2 * kMaxLayerHits + i2];
+      const float z2 = L.sz[2 * kMaxLayerHits + i2];
       const float t12 = (z2 - z1) * C.inv12;
-      unsigned long long w0 = have ? sm01[2 * i1] : 0ull, w1 = have ? sm01[2 * i1 + 1] : 0ull;
+      unsigned long long w0 = have ? L.sm01[2 * i1] : 0ull, w1 = have ? L.sm01[2 * i1 + 1] : 0ull;
       const int nb = __popcll(w0) + __popcll(w1);
       const int nmax = wave_max(nb);
       for (int it = 0; it < nmax; ++it) {
-        if (stream && fill > kTripBuf - kWave) flush();
         const bool act = it < nb;
         int i0 = 0;
         if (act) {
@@ -188,59 +245,89 @@ k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __
           else { i0 = 64 + __ffsll((long long)w1) - 1; w1 &= w1 - 1; }
         }
         bool pass = false;
-        if (act) {
-          const float x0 = sx[i0], y0 = sy[i0], z0 = sz[i0];
-          pass = dl_cut(z0, z1, z2, t12, C) && rtc_cut(x0, y0, x1, y1, x2, y2, C);
-        }
+        if (act) pass = dl_cut(L.sz[i0], z1, z2, t12, C) && rtc_cut(L.sx[i0], L.sy[i0], x1, y1, x2, y2, C);
         const unsigned long long bm = __ballot(pass);
-        if (pass) {
-          const int slot = fill + __popcll(bm & lanemask_lt());
-          if (slot < kTripBuf) stb[slot] = (uint32_t)i0 | ((uint32_t)i1 << 8) | ((uint32_t)i2 << 16);
+        const int c = __popcll(bm);
+        if (c > 0) {
+          if (cur.used + c > cur.cap && !cur.full) {
+            cursor_close(cur, done, T);
+            cursor_open(cur, T, counters);
+            done = 0;
+          }
+          if (cur.cap > 0) {
+            if (pass) {
+              const int slot = cur.start + cur.used + __popcll(bm & lanemask_lt());
+              T.trips[2 * slot] = f;
+              T.trips[2 * slot + 1] = (int32_t)((uint32_t)i0 | ((uint32_t)i1 << 8) | ((uint32_t)i2 << 16));
+            }
+            cur.used += c;
+          }
         }
-        const int np = __popcll(bm);
-        fill += np;
-        total += np;
+        total += c;
       }
       __syncthreads();
     };
-
-    // ---- stream (h1, h2) pairs passing Phi12 into the join
+    // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
     int npend = 0;
-    if (n0 > 0 && n2 > 0) {
-      for (int i1 = 0; i1 < n1; ++i1) {
-        if ((sm01[2 * i1] | sm01[2 * i1 + 1]) == 0ull) continue;
-        const float x1 = sx[kMaxLayerHits + i1], y1 = sy[kMaxLayerHits + i1];
-        for (int base = 0; base < n2; base += kWave) {
-          const int i2 = base + lane;
-          bool p = false;
-          if (i2 < n2)
-            p = cos_cut(x1, y1, sx[2 * kMaxLayerHits + i2], sy[2 * kMaxLayerHits + i2], C.invRR12, C.c12_lo,
-                        C.c12_hi, C.R[1], C.R[2]);
-          const unsigned long long bm = __ballot(p);
-          if (p) spend[npend + __popcll(bm & lanemask_lt())] = (uint32_t)i1 | ((uint32_t)i2 << 8);
-          npend += __popcll(bm);
-          if (npend >= kWave) {
-            __syncthreads();
-            join(kWave);
-            const int rem = npend - kWave;
-            const uint32_t v = lane < rem ? spend[kWave + lane] : 0u;
-            __syncthreads();
-            if (lane < rem) spend[lane] = v;
-            __syncthreads();
-            npend = rem;
-          }
-        }
+    const int n12 = n1 * n2;
+    const float r2 = 1.0f / (float)n2;
+    for (int base = 0; base < n12; base += kWave) {
+      const int p = base + lane;
+      const int i1 = (int)(((float)p + 0.5f) * r2);
+      const int i2 = p - i1 * n2;
+      bool pass = false;
+      if (p < n12 && (L.sm01[2 * i1] | L.sm01[2 * i1 + 1]) != 0ull)
+        pass = cos_cut(L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], L.sx[2 * kMaxLayerHits + i2],
+                       L.sy[2 * kMaxLayerHits + i2], C.invRR12, C.c12_lo, C.c12_hi, C.R[1], C.R[2]);
+      const unsigned long long bm = __ballot(pass);
+      if (pass) L.spend[npend + __popcll(bm & lanemask_lt())] = (uint32_t)i1 | ((uint32_t)i2 << 8);
+      npend += __popcll(bm);
+      if (npend >= kWave) {
+        __syncthreads();
+        join(kWave);
+        const int rem = npend - kWave;
+        const uint32_t v = lane < rem ? L.spend[kWave + lane] : 0u;
+        __syncthreads();
+        if (lane < rem) L.spend[lane] = v;
+        __syncthreads();
+        npend = rem;
       }
-      if (npend > 0) { __syncthreads(); join(npend); }
     }
-    const bool ovf = total > C.max_trip;
-    if (stream || !ovf) flush();
-    if (lane == 0) {
-      counts[3 * f] = total;
-      flags[f] = ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u;
-    }
-    __syncthreads();
+    if (npend > 0) { __syncthreads(); join(npend); }
   }
+  const bool ovf = total > C.max_trip;
+  if (lane == 0) {
+    counts[3 * f] = total;
+    flags[f] = ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u;
+  }
+  // an overflowing frame is rolled back within the current chunk; entries it
+  // left in chunks closed meanwhile are skipped by their frame flag
+  if (ovf && cur.cap > 0) cur.used = cur.id == fid ? fused : 0;
+  __syncthreads();
+  return ovf ? 0 : total;
+}
+
+// End of a wave's cuts: record its last chunk and add its survivors.
+__device__ inline void close_list(const Cursor& cur, int done, int selected, const TripList& T,
+                                  int32_t* __restrict__ counters) {
+  cursor_close(cur, done, T);
+  if (threadIdx.x == 0 && selected > 0) atomicAdd(&counters[0], selected);
+}
+
+// Plain form: one wave per frame, frames dealt cyclically to a static grid
+// (Alg. 1 with the paper's cyclic distribution); survivors go to the wave's
+// chunks of the triplet list.
+__global__ void __launch_bounds__(64)
+k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+       const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
+       int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
+       int32_t* __restrict__ counters) {
+  __shared__ CutLds L;
+  Cursor cur = cursor_init();
+  int done = 0, selected = 0;   // nothing is fitted here
+  for (int f = blockIdx.x; f < F; f += gridDim.x)
+    selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+  close_list(cur, 0, selected, T, counters);
 }
 
 // ================================================================= k_tracks
@@ -283,40 +370,158 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
   return chi2 < (T)C.chi2_trk ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(256)
-k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
-         const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags,
-         const int32_t* __restrict__ trips, int trip_cap, int32_t* __restrict__ counts,
-         int32_t* __restrict__ head, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
-         int32_t* __restrict__ counters) {
-  const int n = min(counters[0], trip_cap);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int f = trips[2 * t];
-    if (flags[f] & MU3E_TRIPLET_OVF) continue;
-    const uint32_t pk = (uint32_t)trips[2 * t + 1];
-    const int g0 = lo[4 * f] + (int)(pk & 0xff);
-    const int g1 = lo[4 * f + 1] + (int)((pk >> 8) & 0xff);
-    const int g2 = lo[4 * f + 2] + (int)((pk >> 16) & 0xff);
-    const int b3 = lo[4 * f + 3], b4 = lo[4 * f + 4];
-    int g3 = -1;
-    float kb = 0.f, c2 = 0.f;
-    int r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
-    if (r < 0) {
-      double kd = 0, cd = 0;
-      r = track_eval<double>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kd, cd);
-      kb = (float)kd;
-      c2 = (float)cd;
-    }
-    if (r != 1) continue;
+// Accepted track: per-frame counts and charge tally, one list entry.
+__device__ inline void push_track(int f, int g0, int g1, int g2, int g3, float kb, float c2,
+                                  int32_t* __restrict__ counts, int32_t* __restrict__ ccnt,
+                                  int32_t* __restrict__ trk, int trk_cap, int32_t* __restrict__ counters) {
+  atomicAdd(&counts[3 * f + 1], 1);
+  atomicAdd(&ccnt[f], kb > 0.f ? 1 : 65536);
+  const int slot = atomicAdd(&counters[1], 1);
+  if (slot >= trk_cap) { atomicOr(&counters[2], ST_TRACK_FULL); return; }
+  int32_t* o = trk + 8 * slot;
+  o[0] = f; o[1] = g0; o[2] = g1; o[3] = g2; o[4] = g3; o[5] = 0;
+  o[6] = __float_as_int(kb);
+  o[7] = __float_as_int(c2);
+}
+
+// Wave-aggregated appends, called by all 64 lanes of a wave with r from
+// track_eval (r == 1 accepted, r < 0 undecided, else nothing): one atomic per
+// list per wave reserves the slots, each lane then writes its own entry.
+__device__ inline void emit_tracks(int r, int f, uint32_t pk, int g0, int g1, int g2, int g3, float kb, float c2,
+                                   int32_t* __restrict__ counts, int32_t* __restrict__ ccnt,
+                                   int32_t* __restrict__ trk, int trk_cap, int32_t* __restrict__ redo, int redo_cap,
+                                   int32_t* __restrict__ counters) {
+  const unsigned long long acc = __ballot(r == 1), und = __ballot(r < 0);
+  int kbase = 0, qbase = 0;
+  if (threadIdx.x == 0) {
+    if (acc) kbase = atomicAdd(&counters[1], __popcll(acc));
+    if (und) qbase = atomicAdd(&counters[5], __popcll(und));
+  }
+  kbase = __shfl(kbase, 0, 64);
+  qbase = __shfl(qbase, 0, 64);
+  const uint64_t lt = lanemask_lt();
+  if (r == 1) {
     atomicAdd(&counts[3 * f + 1], 1);
     atomicAdd(&ccnt[f], kb > 0.f ? 1 : 65536);
-    const int slot = atomicAdd(&counters[1], 1);
-    if (slot >= trk_cap) { atomicOr(&counters[2], ST_TRACK_FULL); continue; }
-    int32_t* o = trk + 8 * slot;
-    o[0] = f; o[1] = g0; o[2] = g1; o[3] = g2; o[4] = g3;
-    o[6] = __float_as_int(kb);
-    o[7] = __float_as_int(c2);
-    o[5] = atomicExch(&head[f], slot);
+    const int slot = kbase + __popcll(acc & lt);
+    if (slot >= trk_cap) {
+      atomicOr(&counters[2], ST_TRACK_FULL);
+    } else {
+      int32_t* o = trk + 8 * slot;
+      o[0] = f; o[1] = g0; o[2] = g1; o[3] = g2; o[4] = g3; o[5] = 0;
+      o[6] = __float_as_int(kb);
+      o[7] = __float_as_int(c2);
+    }
+  } else if (r < 0) {
+    const int q = qbase + __popcll(und & lt);
+    if (q < redo_cap) { redo[2 * q] = f; redo[2 * q + 1] = (int32_t)pk; }
+    else atomicOr(&counters[2], ST_TRACK_FULL);
+  }
+}
+
+__device__ inline void triplet_hits(const int32_t* __restrict__ lo, int f, uint32_t pk, int& g0, int& g1, int& g2,
+                                    int& b3, int& b4) {
+  g0 = lo[4 * f] + (int)(pk & 0xff);
+  g1 = lo[4 * f + 1] + (int)((pk >> 8) & 0xff);
+  g2 = lo[4 * f + 2] + (int)((pk >> 16) & 0xff);
+  b3 = lo[4 * f + 3];
+  b4 = lo[4 * f + 4];
+}
+
+// Float32 track reconstruction of the entries [fitted, count) of every
+// chunk of the triplet list, one wave per chunk; candidates the float32
+// arithmetic cannot decide go to the re-evaluation list (frame, packed
+// indices).
+__global__ void __launch_bounds__(64)
+k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+         const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags, TripList T,
+         int32_t* __restrict__ counts, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
+         int32_t* __restrict__ redo, int redo_cap, int32_t* __restrict__ counters) {
+  const int nch = chunks_granted(T, counters);
+  for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const int32_t* row = T.chunks + 4 * ch;
+    const int start = row[0], n = row[1], from = row[2];
+    for (int base = from; base < n; base += kWave) {
+      const int t = base + (int)threadIdx.x;
+      int r = 0, f = 0, g0 = 0, g1 = 0, g2 = 0, g3 = -1;
+      uint32_t pk = 0;
+      float kb = 0.f, c2 = 0.f;
+      if (t < n) {
+        f = T.trips[2 * (start + t)];
+        pk = (uint32_t)T.trips[2 * (start + t) + 1];
+        if (!(flags[f] & MU3E_TRIPLET_OVF)) {
+          int b3, b4;
+          triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
+          r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
+        }
+      }
+      emit_tracks(r, f, pk, g0, g1, g2, g3, kb, c2, counts, ccnt, trk, trk_cap, redo, redo_cap, counters);
+    }
+  }
+}
+
+// ============================================================ batched form
+// Persistent waves claim `claim` frames at a time from one counter (work
+// stealing over uneven frames), run the Selection Cuts of each frame, and fit
+// the pending survivors of all their frames 64 at a time, so that the lanes
+// of a fit batch span frames.  Entries left unfitted in a chunk closed in the
+// middle of a frame are recorded for k_tracks.  Undecided fits go to the
+// float64 list as in the plain form.
+__global__ void __launch_bounds__(64)
+k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+          const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
+          int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
+          int32_t* __restrict__ trk, int trk_cap, int32_t* __restrict__ redo, int redo_cap,
+          int32_t* __restrict__ counters, int claim) {
+  __shared__ CutLds L;
+  const int lane = threadIdx.x;
+  Cursor cur = cursor_init();
+  int done = 0, selected = 0;
+  auto fit = [&](int k) {   // fit entries [done, done + k) of the current chunk, lane j taking done + j
+    int r = 0, f = 0, g0 = 0, g1 = 0, g2 = 0, g3 = -1;
+    uint32_t pk = 0;
+    float kb = 0.f, c2 = 0.f;
+    if (lane < k) {
+      const int e = cur.start + done + lane;
+      f = T.trips[2 * e];
+      pk = (uint32_t)T.trips[2 * e + 1];
+      int b3, b4;
+      triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
+      r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
+    }
+    emit_tracks(r, f, pk, g0, g1, g2, g3, kb, c2, counts, ccnt, trk, trk_cap, redo, redo_cap, counters);
+    done += k;
+  };
+  for (;;) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&counters[6], claim);
+    base = __shfl(base, 0, 64);
+    if (base >= F) break;
+    const int fe = base + claim < F ? base + claim : F;
+    for (int f = base; f < fe; ++f) {
+      selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+      while (cur.used - done >= kWave) fit(kWave);
+    }
+  }
+  if (cur.used > done) fit(cur.used - done);
+  close_list(cur, done, selected, T, counters);
+}
+
+// Float64 re-evaluation of the undecided candidates of k_tracks.
+__global__ void __launch_bounds__(64)
+k_tracks_redo(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+              const int32_t* __restrict__ lo, Consts C, const int32_t* __restrict__ redo, int redo_cap,
+              int32_t* __restrict__ counts, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
+              int32_t* __restrict__ counters) {
+  const int n = min(counters[5], redo_cap);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int f = redo[2 * t];
+    int g0, g1, g2, b3, b4;
+    triplet_hits(lo, f, (uint32_t)redo[2 * t + 1], g0, g1, g2, b3, b4);
+    int g3 = -1;
+    double kd = 0, cd = 0;
+    if (track_eval<double>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kd, cd) == 1)
+      push_track(f, g0, g1, g2, g3, (float)kd, (float)cd, counts, ccnt, trk, trk_cap, counters);
   }
 }
 
@@ -724,47 +929,12 @@ k_fit(const float* __restrict__ X, const float* __restrict__ Y, const float* __r
 constexpr int kAlignBlocks = 1024;
 constexpr int kAlignMaxSensors = 2048;   // float64 LDS accumulators per block
 
-__device__ inline void align_hit(const float* __restrict__ X, const float* __restrict__ Y,
-                                 const float* __restrict__ Z, const uint16_t* __restrict__ S,
-                                 const float* __restrict__ theta, int g, double* h, int& s, double& ca,
-                                 double& sa) {
-  s = S[g];
-  const double tx = theta[4 * s], ty = theta[4 * s + 1], tz = theta[4 * s + 2], a = theta[4 * s + 3];
-  ca = cos(a);
-  sa = sin(a);
-  const double x = X[g], y = Y[g];
-  h[0] = ca * x - sa * y + tx;
-  h[1] = sa * x + ca * y + ty;
-  h[2] = (double)Z[g] + tz;
-}
-
-__device__ inline bool align_triplet(const float* __restrict__ X, const float* __restrict__ Y,
-                                     const float* __restrict__ Z, const uint16_t* __restrict__ S, int n_hits,
-                                     int n_sensors, const float* __restrict__ theta, const int32_t* tr, double* h,
-                                     int* s, double* ca, double* sa) {
-  for (int k = 0; k < 3; ++k) {
-    const int g = tr[k];
-    if ((unsigned)g >= (unsigned)n_hits) return false;
-    if (S[g] >= n_sensors) return false;
-    align_hit(X, Y, Z, S, theta, g, h + 3 * k, s[k], ca[k], sa[k]);
-  }
-  return true;
-}
-
 __global__ void __launch_bounds__(256)
 k_align_fwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
             const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
             const float* __restrict__ theta, int n_sensors, Consts C, float* __restrict__ chi2) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    double h[9], ca[3], sa[3];
-    int s[3];
-    float c = __builtin_nanf("");
-    if (align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, h, s, ca, sa)) {
-      const Fit<float> f = fit_triplet<float>(h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], h[8], C);
-      if (f.ok) c = f.chi2;
-    }
-    chi2[t] = c;
-  }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    chi2[t] = align_chi2_one(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, C);
 }
 
 // Per block: sum over its triplets of grad_chi2[t] d chi2_t / d theta into
@@ -779,23 +949,15 @@ k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const floa
   for (int j = threadIdx.x; j < np; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    double h[9], ca[3], sa[3];
+    double gs[12];
     int s[3];
-    if (!align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, h, s, ca, sa)) continue;
-    const float w = gchi2[t];
-    double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    float c;
-    if (!fit_chi2_adjoint<float>(h, C, w, c, g)) continue;
+    if (!align_grad_one(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, C, gchi2[t], s, gs)) continue;
     for (int k = 0; k < 3; ++k) {
-      // hit before alignment: x = ca (x' - tx) + sa (y' - ty), y = -sa (x' - tx) + ca (y' - ty)
-      const double gx = g[3 * k], gy = g[3 * k + 1], gz = g[3 * k + 2];
-      const double x0 = X[trip[3 * t + k]], y0 = Y[trip[3 * t + k]];
-      const double dxa = -sa[k] * x0 - ca[k] * y0, dya = ca[k] * x0 - sa[k] * y0;   // d(x', y')/d alpha
       double* a = acc + 4 * s[k];
-      atomicAdd(a + 0, gx);
-      atomicAdd(a + 1, gy);
-      atomicAdd(a + 2, gz);
-      atomicAdd(a + 3, gx * dxa + gy * dya);
+      atomicAdd(a + 0, gs[4 * k]);
+      atomicAdd(a + 1, gs[4 * k + 1]);
+      atomicAdd(a + 2, gs[4 * k + 2]);
+      atomicAdd(a + 3, gs[4 * k + 3]);
     }
   }
   __syncthreads();
@@ -819,19 +981,20 @@ __global__ void k_zero(int32_t* __restrict__ p, int n) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters, trips, trk, vt, vok, ctab, head, ccnt, vbase, vpos, cand, total;
+  size_t counters, chunks, trips, trk, redo, vt, vok, ctab, ccnt, vbase, vpos, cand, total;
 };
 
 Layout layout(int64_t F, int64_t tc, int64_t kc) {
   Layout L;
   size_t o = 0;
   L.counters = o; o += align256(kCounters * sizeof(int32_t));
+  L.chunks = o; o += align256((size_t)(tc / kMinChunk + 1) * 4 * sizeof(int32_t));
   L.trips = o; o += align256((size_t)tc * 2 * sizeof(int32_t));
   L.trk = o; o += align256((size_t)kc * 8 * sizeof(int32_t));
+  L.redo = o; o += align256((size_t)(kc / 8 + 1024) * 2 * sizeof(int32_t));
   L.vt = o; o += align256((size_t)kc * sizeof(VTrack));
   L.vok = o; o += align256((size_t)kc * sizeof(int32_t));
   L.ctab = o; o += align256((size_t)kc * sizeof(int32_t));
-  L.head = o; o += align256((size_t)F * sizeof(int32_t));
   L.ccnt = o; o += align256((size_t)F * sizeof(int32_t));
   L.vbase = o; o += align256((size_t)F * sizeof(int32_t));
   L.vpos = o; o += align256((size_t)F * sizeof(int32_t));
@@ -874,6 +1037,61 @@ int device_cus() {
   return cus;
 }
 
+// Pointers into a caller workspace.
+struct WsView {
+  int32_t *counters, *chunks, *trips, *trk, *redo, *ctab, *ccnt, *vbase, *vpos, *cand, *vok;
+  VTrack* vt;
+  int redo_cap;
+};
+
+WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
+  char* ws = static_cast<char*>(workspace);
+  WsView W;
+  W.counters = reinterpret_cast<int32_t*>(ws + L.counters);
+  W.chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
+  W.trips = reinterpret_cast<int32_t*>(ws + L.trips);
+  W.trk = reinterpret_cast<int32_t*>(ws + L.trk);
+  W.redo = reinterpret_cast<int32_t*>(ws + L.redo);
+  W.vt = reinterpret_cast<VTrack*>(ws + L.vt);
+  W.vok = reinterpret_cast<int32_t*>(ws + L.vok);
+  W.ctab = reinterpret_cast<int32_t*>(ws + L.ctab);
+  W.ccnt = reinterpret_cast<int32_t*>(ws + L.ccnt);
+  W.vbase = reinterpret_cast<int32_t*>(ws + L.vbase);
+  W.vpos = reinterpret_cast<int32_t*>(ws + L.vpos);
+  W.cand = reinterpret_cast<int32_t*>(ws + L.cand);
+  W.redo_cap = track_capacity / 8 + 1024;
+  return W;
+}
+
+// The triplet list of a launch with `waves` appending waves: chunks of about
+// capacity / (2 waves) entries (so that half the list is left to spare for
+// partly filled chunks), clamped to [kMinChunk, kMaxChunk].
+TripList trip_list(const WsView& W, int capacity, int waves) {
+  TripList T;
+  T.trips = W.trips;
+  T.chunks = W.chunks;
+  T.capacity = capacity;
+  int64_t c = waves > 0 ? (int64_t)capacity / (2 * (int64_t)waves) : kMaxChunk;
+  if (c < kMinChunk) c = kMinChunk;
+  if (c > kMaxChunk) c = kMaxChunk;
+  T.chunk = (int)c;
+  return T;
+}
+
+// Vertex stage (Alg. 4) after the track stage of either form.
+void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const WsView& W, uint32_t* flags,
+                   int32_t* counts, float* vtx, int track_capacity, hipStream_t stream, hipEvent_t* ev) {
+  const int gf = (F + 255) / 256 < cus * 8 ? (F + 255) / 256 : cus * 8;
+  hipLaunchKernelGGL(k_vcand, dim3(gf), dim3(256), 0, stream, F, C, flags, counts, W.ccnt, W.vbase, W.vpos, W.cand,
+                     W.counters);
+  hipLaunchKernelGGL(k_vprep_list, dim3(cus * 4), dim3(256), 0, stream, h.x, h.y, h.z, h.n_hits, C, W.trk,
+                     track_capacity, W.counters, W.vbase, W.vpos, W.ctab, W.vt, W.vok);
+  if (ev) (void)hipEventRecord(ev[3], stream);
+  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, C, W.counters, W.cand, W.vbase, W.vpos,
+                     W.ctab, track_capacity, W.vt, W.vok, flags, counts, vtx);
+  if (ev) (void)hipEventRecord(ev[4], stream);
+}
+
 bool hits_ok(const mu3e_hits_t* h) {
   return h && h->n_frames >= 0 && h->n_hits >= 0 &&
          (h->n_frames == 0 || (h->layer_offsets && (h->n_hits == 0 || (h->x && h->y && h->z))));
@@ -895,7 +1113,8 @@ const char* mu3e_status_string(mu3e_status s) {
 }
 
 size_t mu3e_select_workspace_size(int32_t n_frames, int32_t triplet_capacity, int32_t track_capacity) {
-  if (n_frames < 0 || triplet_capacity < 0 || track_capacity < 0) return 0;
+  if (n_frames < 0 || triplet_capacity < 0 || triplet_capacity > kMaxTripletCapacity || track_capacity < 0)
+    return 0;
   return layout(n_frames, triplet_capacity, track_capacity).total;
 }
 
@@ -903,7 +1122,9 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
                                      int32_t* frame_counts, float* frame_vertex, void* workspace,
                                      size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
                                      mu3e_debug_t* dbg, hipStream_t stream, hipEvent_t* ev) {
-  if (!hits_ok(hits) || !params || triplet_capacity < 0 || track_capacity < 0) return MU3E_ERR_INVALID_ARG;
+  if (!hits_ok(hits) || !params || triplet_capacity < 0 || triplet_capacity > kMaxTripletCapacity ||
+      track_capacity < 0)
+    return MU3E_ERR_INVALID_ARG;
   Consts C;
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
   if (C.max_lh > kMaxLayerHits) return MU3E_ERR_UNSUPPORTED;
@@ -911,47 +1132,34 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
   const Layout L = layout(F, triplet_capacity, track_capacity);
   if (!workspace || workspace_bytes < L.total) return MU3E_ERR_CAPACITY;
   if (F > 0 && (!frame_flags || !frame_counts || !frame_vertex)) return MU3E_ERR_INVALID_ARG;
-  char* ws = static_cast<char*>(workspace);
-  int32_t* counters = reinterpret_cast<int32_t*>(ws + L.counters);
-  int32_t* trips = reinterpret_cast<int32_t*>(ws + L.trips);
-  int32_t* trk = reinterpret_cast<int32_t*>(ws + L.trk);
-  VTrack* vt = reinterpret_cast<VTrack*>(ws + L.vt);
-  int32_t* vok = reinterpret_cast<int32_t*>(ws + L.vok);
-  int32_t* ctab = reinterpret_cast<int32_t*>(ws + L.ctab);
-  int32_t* head = reinterpret_cast<int32_t*>(ws + L.head);
-  int32_t* ccnt = reinterpret_cast<int32_t*>(ws + L.ccnt);
-  int32_t* vbase = reinterpret_cast<int32_t*>(ws + L.vbase);
-  int32_t* vpos = reinterpret_cast<int32_t*>(ws + L.vpos);
-  int32_t* cand = reinterpret_cast<int32_t*>(ws + L.cand);
+  const WsView W = ws_view(workspace, L, track_capacity);
+  const int cus = device_cus();
+  // waves of the cuts kernel: 16 per CU, at least enough for 2048 frames each
+  int g1 = cus * 16;
+  if (g1 < (F + 2047) / 2048) g1 = (F + 2047) / 2048;
+  if (g1 > F) g1 = F > 0 ? F : 1;
+  const TripList T = trip_list(W, triplet_capacity, g1);
   if (dbg) {
-    dbg->counters = counters; dbg->triplets = trips; dbg->tracks = trk;
+    dbg->counters = W.counters; dbg->triplets = W.trips; dbg->tracks = W.trk;
     dbg->triplet_capacity = triplet_capacity; dbg->track_capacity = track_capacity;
+    dbg->chunks = W.chunks; dbg->max_chunks = triplet_capacity / kMinChunk + 1; dbg->chunk_size = T.chunk;
   }
   if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return MU3E_ERR_HIP;
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, counters, kCounters);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, W.counters, kCounters);
   if (F == 0) {
     for (int k = 1; ev && k < 5; ++k) (void)hipEventRecord(ev[k], stream);
     return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
   }
-  const int cus = device_cus();
-  const int g1 = F < cus * 16 ? F : cus * 16;
   hipLaunchKernelGGL(k_cuts, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, F,
-                     hits->n_hits, C,
-                     frame_flags, frame_counts, frame_vertex, head, ccnt, trips, triplet_capacity, counters);
+                     hits->n_hits, C, frame_flags, frame_counts, frame_vertex, W.ccnt, T, W.counters);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  hipLaunchKernelGGL(k_tracks, dim3(cus * 8), dim3(256), 0, stream, hits->x, hits->y, hits->z,
-                     hits->layer_offsets, C, frame_flags, trips, triplet_capacity, frame_counts, head, ccnt, trk,
-                     track_capacity, counters);
+  hipLaunchKernelGGL(k_tracks, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, C,
+                     frame_flags, T, frame_counts, W.ccnt, W.trk, track_capacity, W.redo, W.redo_cap, W.counters);
+  hipLaunchKernelGGL(k_tracks_redo, dim3(cus), dim3(kWave), 0, stream, hits->x, hits->y, hits->z,
+                     hits->layer_offsets, C, W.redo, W.redo_cap, frame_counts, W.ccnt, W.trk, track_capacity,
+                     W.counters);
   if (ev) (void)hipEventRecord(ev[2], stream);
-  const int gf = (F + 255) / 256 < cus * 8 ? (F + 255) / 256 : cus * 8;
-  hipLaunchKernelGGL(k_vcand, dim3(gf), dim3(256), 0, stream, F, C, frame_flags, frame_counts, ccnt, vbase, vpos, cand,
-                     counters);
-  hipLaunchKernelGGL(k_vprep_list, dim3(cus * 4), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->n_hits, C,
-                     trk, track_capacity, counters, vbase, vpos, ctab, vt, vok);
-  if (ev) (void)hipEventRecord(ev[3], stream);
-  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, C, counters, cand, vbase, vpos, ctab,
-                     track_capacity, vt, vok, frame_flags, frame_counts, frame_vertex);
-  if (ev) (void)hipEventRecord(ev[4], stream);
+  launch_vertex(*hits, C, F, cus, W, frame_flags, frame_counts, frame_vertex, track_capacity, stream, ev);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
@@ -1050,6 +1258,117 @@ mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, in
   hipLaunchKernelGGL(k_align_reduce, dim3((np + 255) / 256), dim3(256), 0, stream, partial, kAlignBlocks, np,
                      grad_theta);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+struct mu3e_plan {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  mu3e_debug_t dbg;
+  mu3e_tuning_t tuning;
+  // launch arguments, kept so that the same sequence can run eagerly
+  mu3e_hits_t hits;
+  Consts C;
+  WsView W;
+  uint32_t* flags;
+  int32_t* counts;
+  float* vertex;
+  TripList T;
+  int F, P, cus, tcap, kcap;
+};
+
+// The batched sequence: clear counters, persistent cuts + fits, fits left in
+// chunks closed mid-frame, float64 re-evaluation, vertex stage.  ev (nullable, 3 events) brackets the
+// persistent kernel and the rest.
+static void plan_launch(const mu3e_plan& pl, hipStream_t s, hipEvent_t* ev) {
+  const mu3e_hits_t& h = pl.hits;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, pl.W.counters, kCounters);
+  if (pl.F == 0) return;
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(k_batched, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits, pl.C,
+                     pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, pl.W.trk, pl.kcap, pl.W.redo, pl.W.redo_cap,
+                     pl.W.counters, pl.tuning.frames_per_claim);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  hipLaunchKernelGGL(k_tracks, dim3(pl.cus), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.flags, pl.T,
+                     pl.counts, pl.W.ccnt, pl.W.trk, pl.kcap, pl.W.redo, pl.W.redo_cap, pl.W.counters);
+  hipLaunchKernelGGL(k_tracks_redo, dim3(pl.cus), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.W.redo,
+                     pl.W.redo_cap, pl.counts, pl.W.ccnt, pl.W.trk, pl.kcap, pl.W.counters);
+  launch_vertex(h, pl.C, pl.F, pl.cus, pl.W, pl.flags, pl.counts, pl.vertex, pl.kcap, s, nullptr);
+  if (ev) (void)hipEventRecord(ev[2], s);
+}
+
+mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const mu3e_params_t* params,
+                             uint32_t* frame_flags, int32_t* frame_counts, float* frame_vertex, void* workspace,
+                             size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
+                             const mu3e_tuning_t* tuning) {
+  if (!out || !hits_ok(hits) || !params || triplet_capacity < 0 || triplet_capacity > kMaxTripletCapacity ||
+      track_capacity < 0)
+    return MU3E_ERR_INVALID_ARG;
+  *out = nullptr;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (C.max_lh > kMaxLayerHits) return MU3E_ERR_UNSUPPORTED;
+  const int F = hits->n_frames;
+  const Layout L = layout(F, triplet_capacity, track_capacity);
+  if (!workspace || workspace_bytes < L.total) return MU3E_ERR_CAPACITY;
+  if (F > 0 && (!frame_flags || !frame_counts || !frame_vertex)) return MU3E_ERR_INVALID_ARG;
+  const WsView W = ws_view(workspace, L, track_capacity);
+  const int cus = device_cus();
+  mu3e_tuning_t t;
+  t.waves_per_cu = tuning && tuning->waves_per_cu > 0 ? tuning->waves_per_cu : 12;
+  t.frames_per_claim = tuning && tuning->frames_per_claim > 0 ? tuning->frames_per_claim : 4;
+  // persistent: never more waves than can be resident at once
+  int resident = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batched, kWave, 0) != hipSuccess) return MU3E_ERR_HIP;
+  if (resident > 0 && t.waves_per_cu > resident) t.waves_per_cu = resident;
+  int P = cus * t.waves_per_cu;
+  if (P > F) P = F > 0 ? F : 1;
+  mu3e_plan* pl = new (std::nothrow) mu3e_plan;
+  if (!pl) return MU3E_ERR_CAPACITY;
+  pl->tuning = t;
+  pl->dbg.counters = W.counters; pl->dbg.triplets = W.trips; pl->dbg.tracks = W.trk;
+  pl->dbg.triplet_capacity = triplet_capacity; pl->dbg.track_capacity = track_capacity;
+  pl->hits = *hits; pl->C = C; pl->W = W;
+  pl->flags = frame_flags; pl->counts = frame_counts; pl->vertex = frame_vertex;
+  pl->T = trip_list(W, triplet_capacity, P);
+  pl->dbg.chunks = W.chunks; pl->dbg.max_chunks = triplet_capacity / kMinChunk + 1; pl->dbg.chunk_size = pl->T.chunk;
+  pl->F = F; pl->P = P; pl->cus = cus; pl->tcap = triplet_capacity; pl->kcap = track_capacity;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return MU3E_ERR_HIP; }
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    plan_launch(*pl, cs, nullptr);
+    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
+  }
+  ok = ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipStreamDestroy(cs);
+  if (!ok) { delete pl; return MU3E_ERR_HIP; }
+  *out = pl;
+  return MU3E_OK;
+}
+
+mu3e_status mu3e_plan_run(mu3e_plan_t* plan, hipStream_t stream) {
+  if (!plan) return MU3E_ERR_INVALID_ARG;
+  return hipGraphLaunch(plan->exec, stream) == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_plan_run_timed(mu3e_plan_t* plan, hipStream_t stream, hipEvent_t* events) {
+  if (!plan || !events || !events[0] || !events[1] || !events[2]) return MU3E_ERR_INVALID_ARG;
+  plan_launch(*plan, stream, events);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_plan_info(const mu3e_plan_t* plan, mu3e_debug_t* dbg, mu3e_tuning_t* tuning) {
+  if (!plan) return MU3E_ERR_INVALID_ARG;
+  if (dbg) *dbg = plan->dbg;
+  if (tuning) *tuning = plan->tuning;
+  return MU3E_OK;
+}
+
+void mu3e_plan_destroy(mu3e_plan_t* plan) {
+  if (!plan) return;
+  (void)hipGraphExecDestroy(plan->exec);
+  (void)hipGraphDestroy(plan->graph);
+  delete plan;
 }
 
 }  // extern "C"

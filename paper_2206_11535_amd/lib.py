@@ -57,7 +57,12 @@ class Tracks(ctypes.Structure):
 
 class Debug(ctypes.Structure):
     _fields_ = [("counters", ctypes.c_void_p), ("triplets", ctypes.c_void_p), ("tracks", ctypes.c_void_p),
-                ("triplet_capacity", ctypes.c_int32), ("track_capacity", ctypes.c_int32)]
+                ("triplet_capacity", ctypes.c_int32), ("track_capacity", ctypes.c_int32),
+                ("chunks", ctypes.c_void_p), ("max_chunks", ctypes.c_int32), ("chunk_size", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("frames_per_claim", ctypes.c_int32)]
 
 
 def make_params(p: dict) -> Params:
@@ -106,6 +111,17 @@ def load(path: str = LIB_PATH):
     L.mu3e_vertex_workspace_size.argtypes = [I]
     L.mu3e_vertex.restype = ctypes.c_int
     L.mu3e_vertex.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Tracks), ctypes.POINTER(Params), P, P, P, P, Z, P]
+    L.mu3e_plan_create.restype = ctypes.c_int
+    L.mu3e_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Hits), ctypes.POINTER(Params),
+                                   P, P, P, P, Z, I, I, ctypes.POINTER(Tuning)]
+    L.mu3e_plan_run.restype = ctypes.c_int
+    L.mu3e_plan_run.argtypes = [P, P]
+    L.mu3e_plan_run_timed.restype = ctypes.c_int
+    L.mu3e_plan_run_timed.argtypes = [P, P, P]
+    L.mu3e_plan_info.restype = ctypes.c_int
+    L.mu3e_plan_info.argtypes = [P, ctypes.POINTER(Debug), ctypes.POINTER(Tuning)]
+    L.mu3e_plan_destroy.restype = None
+    L.mu3e_plan_destroy.argtypes = [P]
     L.mu3e_align_chi2.restype = ctypes.c_int
     L.mu3e_align_chi2.argtypes = [ctypes.POINTER(Hits), P, I, P, I, ctypes.POINTER(Params), P, P]
     L.mu3e_align_workspace_size.restype = Z
@@ -168,7 +184,7 @@ class Selector:
         L = load()
         self.n_frames = n_frames
         self.params = make_params(params)
-        self.tcap = int(triplet_capacity if triplet_capacity is not None else 64 * n_frames + 4096)
+        self.tcap = int(triplet_capacity if triplet_capacity is not None else 128 * n_frames + 65536)
         self.kcap = int(track_capacity if track_capacity is not None else 16 * n_frames + 4096)
         nb = L.mu3e_select_workspace_size(n_frames, self.tcap, self.kcap)
         if nb == 0 and n_frames > 0:
@@ -197,21 +213,31 @@ class Selector:
         _check(st, "mu3e_select_frames")
 
     def counters(self):
-        """[triplets appended, tracks appended, status bits] (synchronises)."""
+        """[triplets selected, tracks appended, status bits, ..., triplet
+        entries handed out in chunks at index 7, ...] (synchronises)."""
         import torch
-        n = 3
+        n = 9
         base = self.dbg.counters - self.ws.data_ptr()
         return self.ws[base:base + 4 * n].view(torch.int32).cpu().numpy()
 
     def lists(self, hits_offsets: np.ndarray):
-        """Host copies of the triplet and track lists (global hit indices)."""
+        """Host copies of the triplet and track lists (global hit indices);
+        triplets of frames flagged TRIPLET_OVF are left out."""
         import torch
         c = self.counters()
-        nt, nk = min(int(c[0]), self.tcap), min(int(c[1]), self.kcap)
+        nk = min(int(c[1]), self.kcap)
         ws = self.ws
-        tb = self.dbg.triplets - ws.data_ptr()
-        kb = self.dbg.tracks - ws.data_ptr()
-        trips = ws[tb:tb + 8 * nt].view(torch.int32).cpu().numpy().reshape(-1, 2)
+        d = self.dbg
+        nch = min(int(c[7]), d.triplet_capacity) // d.chunk_size if d.chunk_size > 0 else 0
+        cb = d.chunks - ws.data_ptr()
+        ch = ws[cb:cb + 16 * nch].view(torch.int32).cpu().numpy().reshape(-1, 4)
+        tb = d.triplets - ws.data_ptr()
+        allt = ws[tb:tb + 8 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 2)
+        trips = np.concatenate([allt[a:a + n] for a, n in ch[:, :2]]) if nch else np.zeros((0, 2), np.int32)
+        flags = self.flags[:self.n_frames].cpu().numpy().view(np.uint32)
+        if len(trips):
+            trips = trips[(flags[trips[:, 0]] & TRIPLET_OVF) == 0]
+        kb = d.tracks - ws.data_ptr()
         trk = ws[kb:kb + 32 * nk].view(torch.int32).cpu().numpy().reshape(-1, 8)
         lo = np.asarray(hits_offsets)
         f = trips[:, 0].astype(np.int64)
@@ -227,6 +253,46 @@ class Selector:
         F = self.n_frames
         return (self.flags[:F].cpu().numpy().view(np.uint32), self.counts[:F].cpu().numpy(),
                 self.vertex[:F].cpu().numpy())
+
+
+class BatchedSelector(Selector):
+    """The batched persistent form: one hipGraph launch per batch
+    (mu3e_plan_*).  Same outputs as Selector; the plan binds `hits`."""
+
+    def __init__(self, hits: DeviceHits, params: dict, triplet_capacity: int | None = None,
+                 track_capacity: int | None = None, device="cuda", waves_per_cu: int = 0,
+                 frames_per_claim: int = 0):
+        super().__init__(hits.n_frames, params, triplet_capacity, track_capacity, device)
+        L = load()
+        self.hits = hits
+        self._hs = hits.struct()
+        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim))
+        plan = ctypes.c_void_p()
+        _check(L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(self._hs), ctypes.byref(self.params),
+                                  _ptr(self.flags), _ptr(self.counts), _ptr(self.vertex), _ptr(self.ws),
+                                  self.ws.numel(), self.tcap, self.kcap, ctypes.byref(self.tuning)),
+               "mu3e_plan_create")
+        self.plan = plan
+        eff = Tuning()
+        _check(L.mu3e_plan_info(self.plan, ctypes.byref(self.dbg), ctypes.byref(eff)), "mu3e_plan_info")
+        self.effective = (eff.waves_per_cu, eff.frames_per_claim)
+
+    def run(self, hits: DeviceHits = None, stream=None, events=None):
+        """events: optional ctypes array of 3 hipEvent_t; then the plan's
+        kernels are launched directly (no graph) with the events around the
+        persistent kernel (mu3e_plan_run_timed)."""
+        assert hits is None or hits is self.hits, "a plan is bound to the hits it was created with"
+        if events is None:
+            _check(load().mu3e_plan_run(self.plan, _stream(stream)), "mu3e_plan_run")
+        else:
+            _check(load().mu3e_plan_run_timed(self.plan, _stream(stream), ctypes.cast(events, ctypes.c_void_p)),
+                   "mu3e_plan_run_timed")
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan is not None and _lib is not None:
+            _lib.mu3e_plan_destroy(plan)
+            self.plan = None
 
 
 def select_frames(hits: DeviceHits, params: dict, stream=None, **kw):

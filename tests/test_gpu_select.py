@@ -66,7 +66,7 @@ def test_cfg3_mixed_subset(lib):
 def test_cfg4_lifted_caps(lib):
     fs = synth.generate(4, n_frames=120)
     p = lifted_caps()
-    orc, flags, counts = check(lib, fs, p, "cfg4[:120] lifted", triplet_capacity=400 * 120,
+    orc, flags, counts = check(lib, fs, p, "cfg4[:120] lifted", triplet_capacity=1000 * 120,
                                track_capacity=80 * 120)
     assert counts[:, 0].sum() > 20000
 
@@ -244,3 +244,69 @@ def test_full_nominal_sampled(lib):
     keep = (flags & 1) != 0
     assert np.array_equal(keep, (flags & 62) != 0)
     assert np.all(counts >= 0)
+
+
+@pytest.mark.parametrize("cfg,n", [(2, 3000), (3, 5000), (1, 1000)])
+def test_batched_equals_plain_and_oracle(lib, cfg, n):
+    """The batched persistent form gives exactly the plain form's outputs
+    and matches the oracle."""
+    import torch
+    fs = synth.generate(cfg, n_frames=n)
+    p = default_params()
+    dh = lib.to_device(fs)
+    print(f"case: batched cfg{cfg}[:{n}]", flush=True)
+    a = lib.select_frames(dh, p)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=8, frames_per_claim=4)
+    b.run()
+    torch.cuda.synchronize()
+    fa, ca, va = a.result()
+    fb, cb, vb = b.result()
+    assert np.array_equal(fa, fb) and np.array_equal(ca, cb)
+    assert np.array_equal(np.nan_to_num(va), np.nan_to_num(vb))
+    ta, ka, kfa, _ = a.lists(fs.layer_offsets)
+    tb, kb, kfb, c = b.lists(fs.layer_offsets)
+    assert c[2] == 0
+    assert sorted(map(tuple, ta.tolist())) == sorted(map(tuple, tb.tolist()))
+    assert sorted(map(tuple, ka[:, :5].tolist())) == sorted(map(tuple, kb[:, :5].tolist()))
+    orc = oracle.run(fs, p)
+    bad, stats = compare(orc, fb, cb, vb, tb, kb, kfb)
+    assert_parity(bad, stats, f"batched cfg{cfg}")
+
+
+@pytest.mark.parametrize("w,c", [(1, 1), (2, 32), (20, 3)])
+def test_batched_shapes_and_repeat(lib, w, c):
+    """Any shape gives the same result, also on a second run of the plan."""
+    import torch
+    fs = synth.generate(3, n_frames=4000)
+    p = default_params()
+    dh = lib.to_device(fs)
+    ref = lib.select_frames(dh, p)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c)
+    for rep in range(2):
+        b.run()
+        torch.cuda.synchronize()
+        fr, cr, vr = ref.result()
+        fb, cb, vb = b.result()
+        assert np.array_equal(fr, fb) and np.array_equal(cr, cb), (w, c, rep)
+    # the eager, event-bracketed launch of the same plan (outputs cleared first)
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    ev = (ctypes.c_void_p * 3)()
+    for i in range(3):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        ev[i] = e
+    b.flags.fill_(-1)
+    b.counts.fill_(-1)
+    b.run(None, torch.cuda.current_stream(), events=ev)
+    torch.cuda.synchronize()
+    fb, cb, vb = b.result()
+    assert np.array_equal(fr, fb) and np.array_equal(cr, cb) and np.array_equal(np.nan_to_num(vr), np.nan_to_num(vb))
+    ms = ctypes.c_float()
+    assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1]) == 0 and ms.value > 0
+    assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[1], ev[2]) == 0 and ms.value >= 0
+    for i in range(3):
+        hip.hipEventDestroy(ev[i])
