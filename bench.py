@@ -41,8 +41,8 @@ FLOPS_PER_L3_HIT = 8
 FLOPS_PAIR01, FLOPS_PAIR12, FLOPS_JOIN, FLOPS_RTC = 4, 6, 3, 24
 
 # HBM traffic of the roofline kernel on this workload from rocprofv3
-# FETCH_SIZE / WRITE_SIZE, keyed by the hash of the kernel source it was
-# measured on (null once the source changes).
+# FETCH_SIZE / WRITE_SIZE, keyed by "<hash of the kernel sources>|<kernel>"
+# of the build it was measured on (null once the source changes).
 TRAFFIC = {}
 
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X float32 vector (published)
@@ -230,29 +230,36 @@ def main():
     ms_plain, stage_ms, _ = time_steps(plain, dh, stream, hip, a.steps, a.warmup, staged=True)
     fitted, flops, flags = fitted_triplets(plain, fs)
     # ---- batched form (autotuned shape, cached)
-    (w, c), _, _ = autotune.tune(dh, p)
-    batched = lib.BatchedSelector(dh, p, device=dev, waves_per_cu=w, frames_per_claim=c)
+    (w, c, u), _, _ = autotune.tune(dh, p)
+    batched = lib.BatchedSelector(dh, p, device=dev, waves_per_cu=w, frames_per_claim=c, fuse_fits=u)
     ms_batched, _, wall = time_steps(batched, dh, stream, hip, a.steps, a.warmup)
     identical = same_outputs(plain, batched)
-    # the persistent kernel alone: the same sequence launched eagerly with
-    # events around it on the launch stream
-    ev = [hip.events(3) for _ in range(a.steps)]
+    # kernel durations: the same sequence launched eagerly with events around
+    # the persistent kernel and the fit kernel, on the launch stream
+    ev = [hip.events(4) for _ in range(a.steps)]
     for k in range(a.steps):
         batched.run(None, stream, events=ev[k])
     torch.cuda.synchronize()
     ms_kbatched = float(np.mean([hip.elapsed(e[0], e[1]) for e in ev]))
+    ms_ktracks = float(np.mean([hip.elapsed(e[1], e[2]) for e in ev]))
     identical = identical and same_outputs(plain, batched)
     work = cut_work(fs, p)
-    kb_flops = cut_flops(work) + flops
+    fused = bool(batched.effective[2])
+    # algorithmic flops of each kernel (the fused persistent kernel also fits;
+    # the few fits it leaves to k_tracks are counted with it)
+    kernels = {"k_batched": (ms_kbatched, cut_flops(work) + (flops if fused else 0.0)),
+               "k_tracks": (ms_ktracks, 0.0 if fused else flops)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
     if a.copy_probe:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)   # an elementwise kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
-    # roofline of the dominant kernel, the persistent cuts + fits kernel
-    # (algorithmic flops / its measured time)
-    achieved = kb_flops / (ms_kbatched / 1e3) / 1e12
+    # roofline of the dominant kernel of the batched step (algorithmic flops
+    # / its measured time)
+    dom_ms, dom_flops = kernels[dom]
+    achieved = dom_flops / (dom_ms / 1e3) / 1e12
     tracks_achieved = flops / (stage_ms[1] / 1e3) / 1e12
     sh = source_hash()
     out = {
@@ -262,7 +269,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"nominal rate, {F} frames of 64 ns, Poisson(6.4) Michel decays + 5 noise "
                                f"hits/layer, signal in 1% of frames", "frames": F, "form": "batched",
-                   "waves_per_cu": batched.effective[0], "frames_per_claim": batched.effective[1]},
+                   "waves_per_cu": batched.effective[0], "frames_per_claim": batched.effective[1],
+                   "fused_fits": fused},
         "fitted_triplets_per_s": fitted / (ms_batched / 1e3),
         "plain": {"value": F / (ms_plain / 1e3), "ms_per_step": ms_plain,
                   "fitted_triplets_per_s": fitted / (ms_plain / 1e3),
@@ -270,9 +278,10 @@ def main():
                   "k_tracks_tflops": tracks_achieved},
         "batched_equals_plain": identical,
         "kept_fraction": float(np.mean(flags & lib.KEEP)),
-        "roofline": {"kernel": "k_batched", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": TRAFFIC.get(sh),
-                     "kernel_ms": ms_kbatched, "flops_per_launch": kb_flops, "work": work,
+        "roofline": {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": TRAFFIC.get(f"{sh}|{dom}"),
+                     "kernel_ms": dom_ms, "flops_per_launch": dom_flops,
+                     "kernels_ms": {k: v[0] for k, v in kernels.items()}, "work": work,
                      "fitted_triplets": fitted, "source": sh},
         "wall_s_timed": wall,
         "paper_context": "1.4e6 frames/s on a GTX 1080Ti at 1e8 mu/s (Geant4 frames, not this workload)",
@@ -282,14 +291,15 @@ def main():
         dm = lib.to_device(fm, dev)
         sp = lib.Selector(fm.n_frames, p, device=dev)
         msp, _, _ = time_steps(sp, dm, stream, hip, max(3, a.steps // 4), 1)
-        (wm, cm), _, _ = autotune.tune(dm, p)
-        sb = lib.BatchedSelector(dm, p, device=dev, waves_per_cu=wm, frames_per_claim=cm)
+        (wm, cm, um), _, _ = autotune.tune(dm, p)
+        sb = lib.BatchedSelector(dm, p, device=dev, waves_per_cu=wm, frames_per_claim=cm, fuse_fits=um)
         msb, _, _ = time_steps(sb, dm, stream, hip, max(3, a.steps // 4), 1)
         out["mixed"] = {"workload": f"{fm.n_frames} frames, lambda per frame from {{2, 6.4, 12, 20}}",
                         "plain_frames_per_s": fm.n_frames / (msp / 1e3),
                         "batched_frames_per_s": fm.n_frames / (msb / 1e3),
                         "batched_equals_plain": same_outputs(sp, sb),
-                        "waves_per_cu": sb.effective[0], "frames_per_claim": sb.effective[1]}
+                        "waves_per_cu": sb.effective[0], "frames_per_claim": sb.effective[1],
+                        "fused_fits": bool(sb.effective[2])}
         del sp, sb, dm
     if a.align:
         fa = synth.generate(synth.CONFIGS[5])

@@ -208,20 +208,22 @@ mu3e_status mu3e_vertex(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
 
 /* ---- Batched form ------------------------------------------------------
  * A plan captures the whole selection of one batch of frames into a HIP
- * graph around one persistent kernel: waves claim chunks of frames from a
- * shared counter (work stealing over uneven frames), run the Selection Cuts
- * of each frame and fit the pending survivors of all their frames 64 at a
- * time; the float64 re-evaluation and the vertex stage follow in the same
- * graph.  Outputs are identical to mu3e_select_frames.  The plan binds the
- * hit, output and workspace buffers given here: refill them and call
- * mu3e_plan_run again.  Runs of one plan (or of plans sharing a workspace)
- * must not overlap. */
+ * graph around one persistent kernel: waves claim frames_per_claim frames at
+ * a time from a shared counter (work stealing over uneven frames) and run
+ * the Selection Cuts of each frame; with fuse_fits the same waves also fit
+ * the pending survivors of their frames 64 at a time, otherwise a fit kernel
+ * follows in the graph.  The float64 re-evaluation and the vertex stage
+ * follow in the same graph.  Outputs are identical to mu3e_select_frames.
+ * The plan binds the hit, output and workspace buffers given here: refill
+ * them and call mu3e_plan_run again.  Runs of one plan (or of plans sharing
+ * a workspace) must not overlap. */
 typedef struct mu3e_plan mu3e_plan_t;
 
 typedef struct {
-  int32_t waves_per_cu;       /* persistent waves per compute unit (0: default 12;
+  int32_t waves_per_cu;       /* persistent waves per compute unit (0: default 16;
                                  capped by occupancy)                           */
   int32_t frames_per_claim;   /* frames taken per work-stealing claim (0: 4)   */
+  int32_t fuse_fits;          /* 1: the persistent waves also fit (see above)  */
 } mu3e_tuning_t;
 
 /* Workspace as mu3e_select_workspace_size.  tuning may be NULL.  Allocates
@@ -236,9 +238,10 @@ mu3e_status mu3e_plan_create(mu3e_plan_t **plan, const mu3e_hits_t *hits,
 mu3e_status mu3e_plan_run(mu3e_plan_t *plan, hipStream_t stream);
 
 /* The same kernel sequence as mu3e_plan_run, launched directly on the stream
- * (no graph) with events[0..2] (caller-created, timing enabled) recorded
- * before and after the persistent kernel and after the last kernel, so its
- * duration can be measured on the stream it runs on.  Identical outputs. */
+ * (no graph) with events[0..3] (caller-created, timing enabled) recorded
+ * before and after the persistent kernel, after the fit kernel and after the
+ * last kernel, so that kernel durations can be measured on the stream they
+ * run on.  Identical outputs. */
 mu3e_status mu3e_plan_run_timed(mu3e_plan_t *plan, hipStream_t stream, hipEvent_t *events);
 
 /* The plan's debug view (as mu3e_select_frames fills it) and the tuning in

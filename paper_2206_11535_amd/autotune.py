@@ -1,13 +1,15 @@
-"""Autotuner of the batched form: persistent waves per compute unit and
-frames per work-stealing claim.
+"""Autotuner of the batched form: persistent waves per compute unit, frames
+per work-stealing claim, and whether the persistent waves also fit.
 
 Each candidate plan runs the given workload (already resident on the GPU);
-its mean step time over HIP-event-timed repeats is measured and the fastest
+its mean step time over event-timed repeats is measured and the fastest
 shape is cached in tuning_cache.json, keyed by GPU architecture, ROCm
-version and workload class (frames and mean hits per frame, rounded).
+version, a hash of the kernel sources and the workload class (frames and
+mean hits per frame, rounded).
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
@@ -16,14 +18,23 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(PKG, "tuning_cache.json")
 
-WAVES_PER_CU = (4, 6, 8, 12, 16, 20)
+WAVES_PER_CU = (4, 8, 12, 16, 20, 24, 32)
 FRAMES_PER_CLAIM = (1, 2, 4, 8, 16, 32)
+FUSE_FITS = (0, 1)
+
+
+def source_tag() -> str:
+    h = hashlib.sha256()
+    for name in ("mu3e.hip", "mu3e_math.hpp"):
+        with open(os.path.join(PKG, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:10]
 
 
 def workload_key(hits, arch: str) -> str:
     import torch
     hpf = hits.n_hits / max(hits.n_frames, 1)
-    return f"{arch}|rocm{torch.version.hip}|F{hits.n_frames}|hpf{round(hpf / 4) * 4}"
+    return f"{arch}|rocm{torch.version.hip}|src{source_tag()}|F{hits.n_frames}|hpf{round(hpf / 4) * 4}"
 
 
 def load_cache() -> dict:
@@ -50,7 +61,7 @@ def time_plan(sel, reps: int = 5, warmup: int = 2) -> float:
 
 def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: int = 5,
          candidates=None, use_cache: bool = True, verbose: bool = False):
-    """Return ((waves_per_cu, frames_per_claim), ms, table)."""
+    """Return ((waves_per_cu, frames_per_claim, fuse_fits), ms, table)."""
     import torch
     from . import lib
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
@@ -58,24 +69,25 @@ def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: i
     cache = load_cache()
     if use_cache and key in cache:
         e = cache[key]
-        return (e["waves_per_cu"], e["frames_per_claim"]), e["ms"], None
-    cand = candidates or [(w, c) for w in WAVES_PER_CU for c in FRAMES_PER_CLAIM]
+        return (e["waves_per_cu"], e["frames_per_claim"], e["fuse_fits"]), e["ms"], None
+    cand = candidates or [(w, c, u) for u in FUSE_FITS for w in WAVES_PER_CU for c in FRAMES_PER_CLAIM]
     table = []
     seen = set()
-    for w, c in cand:
+    for w, c, u in cand:
         sel = lib.BatchedSelector(hits, params, triplet_capacity, track_capacity, waves_per_cu=w,
-                                  frames_per_claim=c)
+                                  frames_per_claim=c, fuse_fits=u)
         if sel.effective in seen:          # capped by occupancy: same shape as before
             del sel
             continue
         seen.add(sel.effective)
         ms = time_plan(sel, reps)
-        table.append((sel.effective[0], sel.effective[1], ms))
+        table.append((*sel.effective, ms))
         if verbose:
-            print(f"  waves/CU {sel.effective[0]:3d} frames/claim {sel.effective[1]:3d}: {ms:.4f} ms", flush=True)
+            print(f"  waves/CU {sel.effective[0]:3d} frames/claim {sel.effective[1]:3d} fused {sel.effective[2]}: "
+                  f"{ms:.4f} ms", flush=True)
         del sel
-    best = min(table, key=lambda r: r[2])
-    cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "ms": best[2]}
+    best = min(table, key=lambda r: r[3])
+    cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "fuse_fits": best[2], "ms": best[3]}
     with open(CACHE, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
-    return (best[0], best[1]), best[2], table
+    return (best[0], best[1], best[2]), best[3], table

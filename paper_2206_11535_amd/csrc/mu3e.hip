@@ -429,7 +429,9 @@ __device__ inline void triplet_hits(const int32_t* __restrict__ lo, int f, uint3
 }
 
 // Float32 track reconstruction of the entries [fitted, count) of every
-// chunk of the triplet list, one wave per chunk; candidates the float32
+// chunk of the triplet list.  The chunks are cut into slices of 64 entries
+// (one wave each, dealt cyclically to the grid) so that the work spreads
+// over the whole chip whatever the chunk size; candidates the float32
 // arithmetic cannot decide go to the re-evaluation list (frame, packed
 // indices).
 __global__ void __launch_bounds__(64)
@@ -438,35 +440,40 @@ k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* 
          int32_t* __restrict__ counts, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
          int32_t* __restrict__ redo, int redo_cap, int32_t* __restrict__ counters) {
   const int nch = chunks_granted(T, counters);
-  for (int ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+  const int spc = (T.chunk + kWave - 1) / kWave;   // slices per chunk
+  const int64_t nsl = (int64_t)nch * spc;
+  for (int64_t v = blockIdx.x; v < nsl; v += gridDim.x) {
+    const int ch = (int)(v / spc);
     const int32_t* row = T.chunks + 4 * ch;
     const int start = row[0], n = row[1], from = row[2];
-    for (int base = from; base < n; base += kWave) {
-      const int t = base + (int)threadIdx.x;
-      int r = 0, f = 0, g0 = 0, g1 = 0, g2 = 0, g3 = -1;
-      uint32_t pk = 0;
-      float kb = 0.f, c2 = 0.f;
-      if (t < n) {
-        f = T.trips[2 * (start + t)];
-        pk = (uint32_t)T.trips[2 * (start + t) + 1];
-        if (!(flags[f] & MU3E_TRIPLET_OVF)) {
-          int b3, b4;
-          triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
-          r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
-        }
+    const int t = from + (int)(v - (int64_t)ch * spc) * kWave + (int)threadIdx.x;
+    if (from + (int)(v - (int64_t)ch * spc) * kWave >= n) continue;   // wave-uniform: slice past the count
+    int r = 0, f = 0, g0 = 0, g1 = 0, g2 = 0, g3 = -1;
+    uint32_t pk = 0;
+    float kb = 0.f, c2 = 0.f;
+    if (t < n) {
+      f = T.trips[2 * (start + t)];
+      pk = (uint32_t)T.trips[2 * (start + t) + 1];
+      if (!(flags[f] & MU3E_TRIPLET_OVF)) {
+        int b3, b4;
+        triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
+        r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
       }
-      emit_tracks(r, f, pk, g0, g1, g2, g3, kb, c2, counts, ccnt, trk, trk_cap, redo, redo_cap, counters);
     }
+    emit_tracks(r, f, pk, g0, g1, g2, g3, kb, c2, counts, ccnt, trk, trk_cap, redo, redo_cap, counters);
   }
 }
 
 // ============================================================ batched form
 // Persistent waves claim `claim` frames at a time from one counter (work
-// stealing over uneven frames), run the Selection Cuts of each frame, and fit
-// the pending survivors of all their frames 64 at a time, so that the lanes
-// of a fit batch span frames.  Entries left unfitted in a chunk closed in the
-// middle of a frame are recorded for k_tracks.  Undecided fits go to the
-// float64 list as in the plain form.
+// stealing over uneven frames) and run the Selection Cuts of each frame.
+// kFuse: the same wave also fits the pending survivors of its frames 64 at a
+// time (fit batches span frames); entries left unfitted in a chunk closed in
+// the middle of a frame are recorded for k_tracks.  Without kFuse the kernel
+// needs far fewer registers (more resident waves for the latency-bound cuts)
+// and k_tracks fits everything.  Undecided fits go to the float64 list as in
+// the plain form.
+template <bool kFuse>
 __global__ void __launch_bounds__(64)
 k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
           const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
@@ -500,10 +507,14 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
     const int fe = base + claim < F ? base + claim : F;
     for (int f = base; f < fe; ++f) {
       selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
-      while (cur.used - done >= kWave) fit(kWave);
+      if constexpr (kFuse) {
+        while (cur.used - done >= kWave) fit(kWave);
+      }
     }
   }
-  if (cur.used > done) fit(cur.used - done);
+  if constexpr (kFuse) {
+    if (cur.used > done) fit(cur.used - done);
+  }
   close_list(cur, done, selected, T, counters);
 }
 
@@ -1276,24 +1287,31 @@ struct mu3e_plan {
   int F, P, cus, tcap, kcap;
 };
 
-// The batched sequence: clear counters, persistent cuts + fits, fits left in
-// chunks closed mid-frame, float64 re-evaluation, vertex stage.  ev (nullable, 3 events) brackets the
-// persistent kernel and the rest.
+// The batched sequence: clear counters, persistent cuts (and fits), the fits
+// left to k_tracks, float64 re-evaluation, vertex stage.  ev (nullable, 4
+// events): before and after the persistent kernel, after k_tracks, at the end.
 static void plan_launch(const mu3e_plan& pl, hipStream_t s, hipEvent_t* ev) {
   const mu3e_hits_t& h = pl.hits;
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, pl.W.counters, kCounters);
   if (pl.F == 0) return;
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_batched, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits, pl.C,
-                     pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, pl.W.trk, pl.kcap, pl.W.redo, pl.W.redo_cap,
-                     pl.W.counters, pl.tuning.frames_per_claim);
+  if (pl.tuning.fuse_fits)
+    hipLaunchKernelGGL(k_batched<true>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits,
+                       pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, pl.W.trk, pl.kcap, pl.W.redo,
+                       pl.W.redo_cap, pl.W.counters, pl.tuning.frames_per_claim);
+  else
+    hipLaunchKernelGGL(k_batched<false>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits,
+                       pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, pl.W.trk, pl.kcap, pl.W.redo,
+                       pl.W.redo_cap, pl.W.counters, pl.tuning.frames_per_claim);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(k_tracks, dim3(pl.cus), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.flags, pl.T,
+  // fits left by the persistent kernel (all of them without fusion)
+  hipLaunchKernelGGL(k_tracks, dim3(pl.cus * 16), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.flags, pl.T,
                      pl.counts, pl.W.ccnt, pl.W.trk, pl.kcap, pl.W.redo, pl.W.redo_cap, pl.W.counters);
+  if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_tracks_redo, dim3(pl.cus), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.W.redo,
                      pl.W.redo_cap, pl.counts, pl.W.ccnt, pl.W.trk, pl.kcap, pl.W.counters);
   launch_vertex(h, pl.C, pl.F, pl.cus, pl.W, pl.flags, pl.counts, pl.vertex, pl.kcap, s, nullptr);
-  if (ev) (void)hipEventRecord(ev[2], s);
+  if (ev) (void)hipEventRecord(ev[3], s);
 }
 
 mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const mu3e_params_t* params,
@@ -1314,11 +1332,15 @@ mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const m
   const WsView W = ws_view(workspace, L, track_capacity);
   const int cus = device_cus();
   mu3e_tuning_t t;
-  t.waves_per_cu = tuning && tuning->waves_per_cu > 0 ? tuning->waves_per_cu : 12;
+  t.waves_per_cu = tuning && tuning->waves_per_cu > 0 ? tuning->waves_per_cu : 16;
   t.frames_per_claim = tuning && tuning->frames_per_claim > 0 ? tuning->frames_per_claim : 4;
+  t.fuse_fits = tuning ? (tuning->fuse_fits != 0) : 0;
   // persistent: never more waves than can be resident at once
   int resident = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batched, kWave, 0) != hipSuccess) return MU3E_ERR_HIP;
+  const hipError_t oe = t.fuse_fits
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batched<true>, kWave, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batched<false>, kWave, 0);
+  if (oe != hipSuccess) return MU3E_ERR_HIP;
   if (resident > 0 && t.waves_per_cu > resident) t.waves_per_cu = resident;
   int P = cus * t.waves_per_cu;
   if (P > F) P = F > 0 ? F : 1;
@@ -1352,7 +1374,7 @@ mu3e_status mu3e_plan_run(mu3e_plan_t* plan, hipStream_t stream) {
 }
 
 mu3e_status mu3e_plan_run_timed(mu3e_plan_t* plan, hipStream_t stream, hipEvent_t* events) {
-  if (!plan || !events || !events[0] || !events[1] || !events[2]) return MU3E_ERR_INVALID_ARG;
+  if (!plan || !events || !events[0] || !events[1] || !events[2] || !events[3]) return MU3E_ERR_INVALID_ARG;
   plan_launch(*plan, stream, events);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }

@@ -62,7 +62,8 @@ class Debug(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("waves_per_cu", ctypes.c_int32), ("frames_per_claim", ctypes.c_int32)]
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("frames_per_claim", ctypes.c_int32),
+                ("fuse_fits", ctypes.c_int32)]
 
 
 def make_params(p: dict) -> Params:
@@ -139,6 +140,20 @@ def _check(st: int, what: str):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape_tail=(), name="tensor"):
+    """A GPU tensor argument as the C ABI reads it: row-major contiguous,
+    of the given dtype and trailing shape (a contiguous copy is made when
+    needed; a wrong dtype, shape or a host tensor raises)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name}: expected shape [n, {', '.join(map(str, shape_tail))}], got {tuple(t.shape)}")
+    return t.contiguous()
 
 
 def _stream(stream):
@@ -261,12 +276,12 @@ class BatchedSelector(Selector):
 
     def __init__(self, hits: DeviceHits, params: dict, triplet_capacity: int | None = None,
                  track_capacity: int | None = None, device="cuda", waves_per_cu: int = 0,
-                 frames_per_claim: int = 0):
+                 frames_per_claim: int = 0, fuse_fits: int = 0):
         super().__init__(hits.n_frames, params, triplet_capacity, track_capacity, device)
         L = load()
         self.hits = hits
         self._hs = hits.struct()
-        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim))
+        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim), int(fuse_fits))
         plan = ctypes.c_void_p()
         _check(L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(self._hs), ctypes.byref(self.params),
                                   _ptr(self.flags), _ptr(self.counts), _ptr(self.vertex), _ptr(self.ws),
@@ -275,12 +290,12 @@ class BatchedSelector(Selector):
         self.plan = plan
         eff = Tuning()
         _check(L.mu3e_plan_info(self.plan, ctypes.byref(self.dbg), ctypes.byref(eff)), "mu3e_plan_info")
-        self.effective = (eff.waves_per_cu, eff.frames_per_claim)
+        self.effective = (eff.waves_per_cu, eff.frames_per_claim, eff.fuse_fits)
 
     def run(self, hits: DeviceHits = None, stream=None, events=None):
-        """events: optional ctypes array of 3 hipEvent_t; then the plan's
+        """events: optional ctypes array of 4 hipEvent_t; then the plan's
         kernels are launched directly (no graph) with the events around the
-        persistent kernel (mu3e_plan_run_timed)."""
+        persistent kernel and the fit kernel (mu3e_plan_run_timed)."""
         assert hits is None or hits is self.hits, "a plan is bound to the hits it was created with"
         if events is None:
             _check(load().mu3e_plan_run(self.plan, _stream(stream)), "mu3e_plan_run")
@@ -305,6 +320,7 @@ def fit_triplets(hits: DeviceHits, trip, params: dict, stream=None):
     """trip: int32 cuda tensor [n, 3] of global hit indices -> float32 [n, 8]."""
     import torch
     L = load()
+    trip = _dev(trip, torch.int32, (3,), "trip")
     n = int(trip.shape[0])
     out = torch.empty((max(n, 1), 8), dtype=torch.float32, device=trip.device)
     hs = hits.struct()
@@ -319,6 +335,8 @@ def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=Non
     (flags [F], combos [F], vertex [F, 4])."""
     import torch
     L = load()
+    track_hits = _dev(track_hits, torch.int32, (4,), "track_hits")
+    frame_offsets = _dev(frame_offsets, torch.int32, (), "frame_offsets")
     F = int(frame_offsets.shape[0]) - 1
     n = int(track_hits.shape[0])
     dev = frame_offsets.device
@@ -340,6 +358,8 @@ def align_chi2(hits: DeviceHits, trip, theta, params: dict, stream=None):
     cuda tensors; trip int32 [n, 3])."""
     import torch
     L = load()
+    trip = _dev(trip, torch.int32, (3,), "trip")
+    theta = _dev(theta, torch.float32, (4,), "theta")
     n = int(trip.shape[0])
     out = torch.empty(max(n, 1), dtype=torch.float32, device=theta.device)
     hs = hits.struct()
@@ -353,7 +373,12 @@ def align_backward(hits: DeviceHits, trip, theta, params: dict, grad_chi2, strea
     """d(sum_t grad_chi2[t] chi2_t) / d theta, float32 [S, 4]."""
     import torch
     L = load()
+    trip = _dev(trip, torch.int32, (3,), "trip")
+    theta = _dev(theta, torch.float32, (4,), "theta")
+    grad_chi2 = _dev(grad_chi2, torch.float32, (), "grad_chi2")
     n = int(trip.shape[0])
+    if int(grad_chi2.shape[0]) != n:
+        raise ValueError("grad_chi2: one entry per triplet expected")
     S = int(theta.shape[0])
     nb = L.mu3e_align_workspace_size(S)
     if nb == 0:

@@ -93,3 +93,28 @@ def test_weighted_backward(setup):
     g = lib.align_backward(dh, torch.from_numpy(trip).cuda(), th, p, torch.from_numpy(w).cuda()).cpu().numpy()
     _, gref = oracle.align_loss_grad(fs, trip, np.zeros((S, 4)), p, weight=w.astype(np.float64))
     assert np.linalg.norm(g - gref) <= 1e-3 * np.linalg.norm(gref)
+
+
+def test_strided_inputs(setup):
+    """Tensors that are not row-major (a Fortran-ordered triplet array, a
+    transposed theta) give the same results: the binding hands the C ABI
+    contiguous copies."""
+    import torch
+    lib, fs, p, trip, dh = setup
+    S = synth.N_SENSORS
+    rng = np.random.default_rng(4)
+    th32 = np.concatenate([rng.normal(0, 0.02, (S, 3)), rng.normal(0, 2e-4, (S, 1))], 1).astype(np.float32)
+    tc = torch.from_numpy(np.ascontiguousarray(trip)).cuda()
+    tf = torch.from_numpy(np.asfortranarray(trip)).cuda()
+    assert not tf.is_contiguous()
+    thc = torch.from_numpy(th32).cuda()
+    tht = torch.from_numpy(np.ascontiguousarray(th32.T)).cuda().t()
+    assert not tht.is_contiguous()
+    a = lib.align_chi2(dh, tc, thc, p).cpu().numpy()
+    b = lib.align_chi2(dh, tf, tht, p).cpu().numpy()
+    assert np.array_equal(a, b)
+    w = torch.ones(len(trip), dtype=torch.float32, device="cuda")
+    ga = lib.align_backward(dh, tc, thc, p, w).cpu().numpy()
+    gb = lib.align_backward(dh, tf, tht, p, w).cpu().numpy()
+    # float64 accumulation in arbitrary atomic order: equal up to its rounding
+    assert np.allclose(ga, gb, rtol=1e-6, atol=1e-6 * np.abs(ga).max())

@@ -246,17 +246,17 @@ def test_full_nominal_sampled(lib):
     assert np.all(counts >= 0)
 
 
-@pytest.mark.parametrize("cfg,n", [(2, 3000), (3, 5000), (1, 1000)])
-def test_batched_equals_plain_and_oracle(lib, cfg, n):
+@pytest.mark.parametrize("cfg,n,fuse", [(2, 3000, 0), (3, 5000, 1), (1, 1000, 0), (2, 2000, 1)])
+def test_batched_equals_plain_and_oracle(lib, cfg, n, fuse):
     """The batched persistent form gives exactly the plain form's outputs
     and matches the oracle."""
     import torch
     fs = synth.generate(cfg, n_frames=n)
     p = default_params()
     dh = lib.to_device(fs)
-    print(f"case: batched cfg{cfg}[:{n}]", flush=True)
+    print(f"case: batched cfg{cfg}[:{n}] fused={fuse}", flush=True)
     a = lib.select_frames(dh, p)
-    b = lib.BatchedSelector(dh, p, waves_per_cu=8, frames_per_claim=4)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=8, frames_per_claim=4, fuse_fits=fuse)
     b.run()
     torch.cuda.synchronize()
     fa, ca, va = a.result()
@@ -273,15 +273,16 @@ def test_batched_equals_plain_and_oracle(lib, cfg, n):
     assert_parity(bad, stats, f"batched cfg{cfg}")
 
 
-@pytest.mark.parametrize("w,c", [(1, 1), (2, 32), (20, 3)])
-def test_batched_shapes_and_repeat(lib, w, c):
+@pytest.mark.parametrize("w,c,fuse", [(1, 1, 1), (2, 32, 0), (20, 3, 1), (32, 8, 0)])
+def test_batched_shapes_and_repeat(lib, w, c, fuse):
     """Any shape gives the same result, also on a second run of the plan."""
     import torch
     fs = synth.generate(3, n_frames=4000)
     p = default_params()
     dh = lib.to_device(fs)
     ref = lib.select_frames(dh, p)
-    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c)
+    print(f"case: batched shape {w} waves/CU, {c} frames/claim, fused={fuse}", flush=True)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=fuse)
     for rep in range(2):
         b.run()
         torch.cuda.synchronize()
@@ -294,8 +295,8 @@ def test_batched_shapes_and_repeat(lib, w, c):
     hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
     hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
     hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
-    ev = (ctypes.c_void_p * 3)()
-    for i in range(3):
+    ev = (ctypes.c_void_p * 4)()
+    for i in range(4):
         e = ctypes.c_void_p()
         assert hip.hipEventCreate(ctypes.byref(e)) == 0
         ev[i] = e
@@ -308,5 +309,6 @@ def test_batched_shapes_and_repeat(lib, w, c):
     ms = ctypes.c_float()
     assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1]) == 0 and ms.value > 0
     assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[1], ev[2]) == 0 and ms.value >= 0
-    for i in range(3):
+    assert hip.hipEventElapsedTime(ctypes.byref(ms), ev[2], ev[3]) == 0 and ms.value >= 0
+    for i in range(4):
         hip.hipEventDestroy(ev[i])
