@@ -308,7 +308,7 @@ def main():
         sa.run(da, stream)
         torch.cuda.synchronize()
         _, tracks, _, _ = sa.lists(fa.layer_offsets)
-        trip = np.concatenate([tracks[:, [1, 2, 3]], tracks[:, [2, 3, 4]]]).astype(np.int32)
+        trip = np.ascontiguousarray(np.concatenate([tracks[:, [1, 2, 3]], tracks[:, [2, 3, 4]]]), dtype=np.int32)
         tt = torch.from_numpy(trip).to(dev)
         theta = torch.zeros((synth.N_SENSORS, 4), dtype=torch.float32, device=dev)
         gch = torch.ones(len(trip), dtype=torch.float32, device=dev)

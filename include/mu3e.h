@@ -103,12 +103,12 @@ typedef struct {
 /* Optional debug view, filled on return of mu3e_select_frames (host struct
  * holding device pointers into the caller's workspace).  The triplet list
  * is handed out to the waves of the cuts kernel in chunks (one atomic per
- * chunk); a frame's triplets may span chunks.  After the stream is
- * synchronised:
+ * chunk); a frame's triplets may span chunks.  The track stage stores its
+ * result for every triplet in place (no shared counter).  After the stream
+ * is synchronised:
  *   counters[0]  triplets selected in total (true count)
- *   counters[1]  tracks appended to the track list (true count, may exceed
- *                track_capacity)
- *   counters[2]  status bits: 1 the triplet list was full, 2 track list
+ *   counters[2]  status bits: 1 the triplet list was full, 2 the float64
+ *                re-evaluation list or the vertex-stage track table was
  *                full, 4 a frame's layer_offsets were malformed (decreasing,
  *                negative or beyond n_hits; that frame was skipped)
  *   counters[7]  triplet entries handed out in chunks of a fixed size
@@ -120,10 +120,14 @@ typedef struct {
  *                and chunk c starts at c * chunk size
  *   triplets     [triplet_capacity][2]: frame, packed frame-local
  *                indices i0 | i1 << 8 | i2 << 16 (hit = layer_offsets[4f+l] + il)
- *   tracks       [track_capacity][8]: frame, hit0, hit1, hit2, hit3, 0,
- *                float bits of kappa_bar, float bits of chi2_global
+ *   tracks       [triplet_capacity][4], parallel to triplets: code (1 the
+ *                triplet starts an accepted track, 0 not, 2 undecided: only
+ *                when the re-evaluation list was full), frame-local
+ *                layer-3 index i3, float bits of kappa_bar, float bits of
+ *                chi2_global
  * Triplets of frames flagged MU3E_TRIPLET_OVF may appear in the list; they
- * are never fitted. */
+ * are never fitted (code 0).  Accepted tracks per frame are in
+ * frame_counts[3f + 1]. */
 typedef struct {
   const int32_t *counters;
   const int32_t *triplets;
@@ -136,8 +140,8 @@ typedef struct {
 const char *mu3e_status_string(mu3e_status s);
 
 /* Workspace bytes for mu3e_select_frames over n_frames frames with room for
- * triplet_capacity (<= 2^30) selected triplets and track_capacity tracks in
- * total.  The triplet list is shared by all waves in chunks of
+ * triplet_capacity (<= 2^30) selected triplets and track_capacity tracks of
+ * vertex candidate frames in total.  The triplet list is shared by all waves in chunks of
  * triplet_capacity / (2 * waves) entries (clamped to [64, 4096]), so allow
  * about twice the expected number of selected triplets; a run whose lists
  * fill up reports it in counters[2] (mu3e_debug_t); its outputs are then

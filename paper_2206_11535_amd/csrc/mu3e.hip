@@ -39,12 +39,13 @@ constexpr int kCounters = 64;                // int32 counters at the workspace 
 constexpr int kMinChunk = 64;                // triplet-list chunk sizes lie in [64, 4096]
 constexpr int kMaxChunk = 4096;
 constexpr int kMaxTripletCapacity = 1 << 30; // keeps the chunk bump counter within int32
+constexpr int kClaimRanges = 8;              // claim counters of the batched form
 
-// counters: [0] triplets selected, [1] tracks appended, [2] status bits,
-// [3] candidate frames of the vertex stage, [4] their track-table size,
-// [5] track candidates re-evaluated in float64, [6] frame claim counter of
-// the batched form, [7] triplet-list entries handed out in chunks (also
-// past the capacity: each grant adds one chunk)
+// counters: [0] triplets selected, [2] status bits, [3] candidate frames of
+// the vertex stage, [4] their track-table size, [5] entries queued for the
+// float64 re-evaluation, [16 .. 23] frame claim counters of the batched
+// form, [7] triplet-list entries handed out in chunks (also past the capacity:
+// each grant adds one chunk), [9] and [10] lengths of the slice tables
 enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
 
 // ----------------------------------------------------------- triplet list
@@ -370,52 +371,52 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
   return chi2 < (T)C.chi2_trk ? 1 : 0;
 }
 
-// Accepted track: per-frame counts and charge tally, one list entry.
-__device__ inline void push_track(int f, int g0, int g1, int g2, int g3, float kb, float c2,
-                                  int32_t* __restrict__ counts, int32_t* __restrict__ ccnt,
-                                  int32_t* __restrict__ trk, int trk_cap, int32_t* __restrict__ counters) {
-  atomicAdd(&counts[3 * f + 1], 1);
-  atomicAdd(&ccnt[f], kb > 0.f ? 1 : 65536);
-  const int slot = atomicAdd(&counters[1], 1);
-  if (slot >= trk_cap) { atomicOr(&counters[2], ST_TRACK_FULL); return; }
-  int32_t* o = trk + 8 * slot;
-  o[0] = f; o[1] = g0; o[2] = g1; o[3] = g2; o[4] = g3; o[5] = 0;
-  o[6] = __float_as_int(kb);
-  o[7] = __float_as_int(c2);
+// ----------------------------------------------------------- track results
+// Results of the track stage are stored in place, parallel to the triplet
+// list, so that no shared counter is needed: entry e has res[4e .. 4e+3] =
+// {code, i3, kappa_bar bits, chi2 bits}.  TR_ACCEPT: accepted track, i3 its
+// frame-local layer-3 hit; TR_REJECT: rejected, or not fitted because its
+// frame overflowed; TR_REDO: float32 could not decide, the entry index is
+// queued for the float64 re-evaluation, which rewrites the result.
+enum { TR_REJECT = 0, TR_ACCEPT = 1, TR_REDO = 2 };
+
+struct TrackOut {
+  int32_t* res;      // [triplet capacity][4]
+  int32_t* redo;     // [redo_cap] entry indices
+  int redo_cap;
+  int32_t* counts;   // per-frame counts [3F]; tracks at 3f + 1
+  int32_t* ccnt;     // per-frame charge tally: +1 per e+, +65536 per e-
+};
+
+__device__ inline void store_result(int32_t* __restrict__ res, int e, int code, int i3, float kb, float c2) {
+  *reinterpret_cast<int4*>(res + 4 * e) = make_int4(code, i3, __float_as_int(kb), __float_as_int(c2));
 }
 
-// Wave-aggregated appends, called by all 64 lanes of a wave with r from
-// track_eval (r == 1 accepted, r < 0 undecided, else nothing): one atomic per
-// list per wave reserves the slots, each lane then writes its own entry.
-__device__ inline void emit_tracks(int r, int f, uint32_t pk, int g0, int g1, int g2, int g3, float kb, float c2,
-                                   int32_t* __restrict__ counts, int32_t* __restrict__ ccnt,
-                                   int32_t* __restrict__ trk, int trk_cap, int32_t* __restrict__ redo, int redo_cap,
-                                   int32_t* __restrict__ counters) {
-  const unsigned long long acc = __ballot(r == 1), und = __ballot(r < 0);
-  int kbase = 0, qbase = 0;
-  if (threadIdx.x == 0) {
-    if (acc) kbase = atomicAdd(&counters[1], __popcll(acc));
-    if (und) qbase = atomicAdd(&counters[5], __popcll(und));
+__device__ inline void tally_track(const TrackOut& O, int f, float kb) {
+  atomicAdd(&O.counts[3 * f + 1], 1);
+  atomicAdd(&O.ccnt[f], kb > 0.f ? 1 : 65536);
+}
+
+// Called by all 64 lanes of a wave; a lane with active == false holds no
+// entry.  r from track_eval: 1 accepted, 0 rejected, -1 undecided; the
+// undecided entries of the wave are queued with one atomic.
+__device__ inline void emit_result(bool active, int r, int e, int f, int i3, float kb, float c2,
+                                   const TrackOut& O, int32_t* __restrict__ counters) {
+  const unsigned long long und = __ballot(active && r < 0);
+  int qbase = 0;
+  if (und != 0ull) {
+    if (threadIdx.x == 0) qbase = atomicAdd(&counters[5], __popcll(und));
+    qbase = __shfl(qbase, 0, 64);
   }
-  kbase = __shfl(kbase, 0, 64);
-  qbase = __shfl(qbase, 0, 64);
-  const uint64_t lt = lanemask_lt();
-  if (r == 1) {
-    atomicAdd(&counts[3 * f + 1], 1);
-    atomicAdd(&ccnt[f], kb > 0.f ? 1 : 65536);
-    const int slot = kbase + __popcll(acc & lt);
-    if (slot >= trk_cap) {
-      atomicOr(&counters[2], ST_TRACK_FULL);
-    } else {
-      int32_t* o = trk + 8 * slot;
-      o[0] = f; o[1] = g0; o[2] = g1; o[3] = g2; o[4] = g3; o[5] = 0;
-      o[6] = __float_as_int(kb);
-      o[7] = __float_as_int(c2);
-    }
-  } else if (r < 0) {
-    const int q = qbase + __popcll(und & lt);
-    if (q < redo_cap) { redo[2 * q] = f; redo[2 * q + 1] = (int32_t)pk; }
+  if (!active) return;
+  if (r < 0) {
+    const int q = qbase + __popcll(und & lanemask_lt());
+    if (q < O.redo_cap) O.redo[q] = e;
     else atomicOr(&counters[2], ST_TRACK_FULL);
+    store_result(O.res, e, TR_REDO, 0, 0.f, 0.f);
+  } else {
+    store_result(O.res, e, r == 1 ? TR_ACCEPT : TR_REJECT, i3, kb, c2);
+    if (r == 1) tally_track(O, f, kb);
   }
 }
 
@@ -428,44 +429,102 @@ __device__ inline void triplet_hits(const int32_t* __restrict__ lo, int f, uint3
   b4 = lo[4 * f + 4];
 }
 
+// Track reconstruction of one list entry (frame f, packed indices pk) in T;
+// i3 is the frame-local layer-3 hit of an accepted track.
+template <class T>
+__device__ inline int fit_entry(const float* __restrict__ X, const float* __restrict__ Y,
+                                const float* __restrict__ Z, const int32_t* __restrict__ lo, const Consts& C, int f,
+                                uint32_t pk, int& i3, T& kb, T& c2) {
+  int g0, g1, g2, b3, b4, g3 = -1;
+  triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
+  const int r = track_eval<T>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
+  i3 = g3 >= 0 ? g3 - b3 : 0;
+  return r;
+}
+
+// ------------------------------------------------------------ slice tables
+// The non-empty 64-entry slices of the granted chunks, packed as
+// chunk * 64 + slice (a chunk holds at most kMaxChunk = 64 * 64 entries).
+// fit: slices of [fitted, count), the entries k_tracks fits; all: slices of
+// [0, count).  counters[9] and counters[10] hold their lengths.
+struct Slices {
+  int32_t* fit;
+  int32_t* all;
+};
+
+__device__ inline int block_exclusive_scan(int v, int* tmp, int& total) {
+  // 1024 threads: inclusive Hillis-Steele scan in LDS
+  const int i = threadIdx.x;
+  tmp[i] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int a = i >= o ? tmp[i - o] : 0;
+    __syncthreads();
+    tmp[i] += a;
+    __syncthreads();
+  }
+  const int incl = tmp[i];
+  total = tmp[1023];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(1024)
+k_slices(TripList T, Slices S, int32_t* __restrict__ counters) {
+  __shared__ int tmp[1024];
+  const int nch = chunks_granted(T, counters);
+  int base_f = 0, base_a = 0;
+  for (int c0 = 0; c0 < nch; c0 += 1024) {
+    const int c = c0 + (int)threadIdx.x;
+    int nf = 0, na = 0, from = 0;
+    if (c < nch) {
+      const int n = T.chunks[4 * c + 1];
+      from = T.chunks[4 * c + 2];
+      na = (n + kWave - 1) / kWave;
+      nf = from < n ? (n - from + kWave - 1) / kWave : 0;
+    }
+    int tf, ta;
+    const int of = block_exclusive_scan(nf, tmp, tf);
+    const int oa = block_exclusive_scan(na, tmp, ta);
+    for (int j = 0; j < nf; ++j) S.fit[base_f + of + j] = c * kWave + j;
+    for (int j = 0; j < na; ++j) S.all[base_a + oa + j] = c * kWave + j;
+    base_f += tf;
+    base_a += ta;
+  }
+  if (threadIdx.x == 0) {
+    counters[9] = base_f;
+    counters[10] = base_a;
+  }
+}
+
 // Float32 track reconstruction of the entries [fitted, count) of every
-// chunk of the triplet list.  The chunks are cut into slices of 64 entries
-// (one wave each, dealt cyclically to the grid) so that the work spreads
-// over the whole chip whatever the chunk size; candidates the float32
-// arithmetic cannot decide go to the re-evaluation list (frame, packed
-// indices).
+// chunk, one wave per 64-entry slice (dealt cyclically to the grid);
+// candidates the float32 arithmetic cannot decide go to the float64 list.
 __global__ void __launch_bounds__(64)
 k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
-         const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags, TripList T,
-         int32_t* __restrict__ counts, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
-         int32_t* __restrict__ redo, int redo_cap, int32_t* __restrict__ counters) {
-  const int nch = chunks_granted(T, counters);
-  const int spc = (T.chunk + kWave - 1) / kWave;   // slices per chunk
-  const int64_t nsl = (int64_t)nch * spc;
-  for (int64_t v = blockIdx.x; v < nsl; v += gridDim.x) {
-    const int ch = (int)(v / spc);
-    const int32_t* row = T.chunks + 4 * ch;
+         const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags, TripList T, Slices S,
+         TrackOut O, int32_t* __restrict__ counters) {
+  const int ns = counters[9];
+  for (int v = blockIdx.x; v < ns; v += gridDim.x) {
+    const int pkd = S.fit[v];
+    const int32_t* row = T.chunks + 4 * (pkd / kWave);
     const int start = row[0], n = row[1], from = row[2];
-    const int t = from + (int)(v - (int64_t)ch * spc) * kWave + (int)threadIdx.x;
-    if (from + (int)(v - (int64_t)ch * spc) * kWave >= n) continue;   // wave-uniform: slice past the count
-    int r = 0, f = 0, g0 = 0, g1 = 0, g2 = 0, g3 = -1;
-    uint32_t pk = 0;
+    const int t = from + (pkd % kWave) * kWave + (int)threadIdx.x;
+    const bool active = t < n;
+    const int e = start + t;
+    int r = 0, f = 0, i3 = 0;
     float kb = 0.f, c2 = 0.f;
-    if (t < n) {
-      f = T.trips[2 * (start + t)];
-      pk = (uint32_t)T.trips[2 * (start + t) + 1];
-      if (!(flags[f] & MU3E_TRIPLET_OVF)) {
-        int b3, b4;
-        triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
-        r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
-      }
+    if (active) {
+      f = T.trips[2 * e];
+      if (!(flags[f] & MU3E_TRIPLET_OVF))
+        r = fit_entry<float>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kb, c2);
     }
-    emit_tracks(r, f, pk, g0, g1, g2, g3, kb, c2, counts, ccnt, trk, trk_cap, redo, redo_cap, counters);
+    emit_result(active, r, e, f, i3, kb, c2, O, counters);
   }
 }
 
 // ============================================================ batched form
-// Persistent waves claim `claim` frames at a time from one counter (work
+// Persistent waves claim `claim` frames at a time from shared counters (work
 // stealing over uneven frames) and run the Selection Cuts of each frame.
 // kFuse: the same wave also fits the pending survivors of its frames 64 at a
 // time (fit batches span frames); entries left unfitted in a chunk closed in
@@ -478,37 +537,44 @@ __global__ void __launch_bounds__(64)
 k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
           const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
           int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
-          int32_t* __restrict__ trk, int trk_cap, int32_t* __restrict__ redo, int redo_cap,
-          int32_t* __restrict__ counters, int claim) {
+          TrackOut O, int32_t* __restrict__ counters, int claim) {
   __shared__ CutLds L;
   const int lane = threadIdx.x;
   Cursor cur = cursor_init();
   int done = 0, selected = 0;
   auto fit = [&](int k) {   // fit entries [done, done + k) of the current chunk, lane j taking done + j
-    int r = 0, f = 0, g0 = 0, g1 = 0, g2 = 0, g3 = -1;
-    uint32_t pk = 0;
+    const bool active = lane < k;
+    const int e = cur.start + done + lane;
+    int r = 0, f = 0, i3 = 0;
     float kb = 0.f, c2 = 0.f;
-    if (lane < k) {
-      const int e = cur.start + done + lane;
+    if (active) {
       f = T.trips[2 * e];
-      pk = (uint32_t)T.trips[2 * e + 1];
-      int b3, b4;
-      triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
-      r = track_eval<float>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
+      r = fit_entry<float>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kb, c2);
     }
-    emit_tracks(r, f, pk, g0, g1, g2, g3, kb, c2, counts, ccnt, trk, trk_cap, redo, redo_cap, counters);
+    emit_result(active, r, e, f, i3, kb, c2, O, counters);
     done += k;
   };
-  for (;;) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(&counters[6], claim);
-    base = __shfl(base, 0, 64);
-    if (base >= F) break;
-    const int fe = base + claim < F ? base + claim : F;
-    for (int f = base; f < fe; ++f) {
-      selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
-      if constexpr (kFuse) {
-        while (cur.used - done >= kWave) fit(kWave);
+  // The frames are split into kClaimRanges ranges with a claim counter each
+  // (counters[16 + k]), so that claims spread over several addresses; a wave
+  // starts in range blockIdx.x % kClaimRanges and moves on when it is used up.
+  for (int i = 0; i < kClaimRanges; ++i) {
+    const int k = (int)((blockIdx.x + i) % kClaimRanges);
+    const int r0 = (int)((int64_t)F * k / kClaimRanges), r1 = (int)((int64_t)F * (k + 1) / kClaimRanges);
+    int32_t* ctr = &counters[16 + k];
+    for (;;) {
+      int base = r1;
+      if (lane == 0) {
+        const int seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen < r1 - r0) base = r0 + atomicAdd(ctr, claim);
+      }
+      base = __shfl(base, 0, 64);
+      if (base >= r1) break;
+      const int fe = base + claim < r1 ? base + claim : r1;
+      for (int f = base; f < fe; ++f) {
+        selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+        if constexpr (kFuse) {
+          while (cur.used - done >= kWave) fit(kWave);
+        }
       }
     }
   }
@@ -518,21 +584,20 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
   close_list(cur, done, selected, T, counters);
 }
 
-// Float64 re-evaluation of the undecided candidates of k_tracks.
+// Float64 re-evaluation of the entries queued by k_tracks (or the fused
+// batched kernel); rewrites their results.
 __global__ void __launch_bounds__(64)
 k_tracks_redo(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
-              const int32_t* __restrict__ lo, Consts C, const int32_t* __restrict__ redo, int redo_cap,
-              int32_t* __restrict__ counts, int32_t* __restrict__ ccnt, int32_t* __restrict__ trk, int trk_cap,
-              int32_t* __restrict__ counters) {
-  const int n = min(counters[5], redo_cap);
+              const int32_t* __restrict__ lo, Consts C, TripList T, TrackOut O, int32_t* __restrict__ counters) {
+  const int n = min(counters[5], O.redo_cap);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int f = redo[2 * t];
-    int g0, g1, g2, b3, b4;
-    triplet_hits(lo, f, (uint32_t)redo[2 * t + 1], g0, g1, g2, b3, b4);
-    int g3 = -1;
+    const int e = O.redo[t];
+    const int f = T.trips[2 * e];
+    int i3 = 0;
     double kd = 0, cd = 0;
-    if (track_eval<double>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kd, cd) == 1)
-      push_track(f, g0, g1, g2, g3, (float)kd, (float)cd, counts, ccnt, trk, trk_cap, counters);
+    const int r = fit_entry<double>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kd, cd);
+    store_result(O.res, e, r == 1 ? TR_ACCEPT : TR_REJECT, i3, (float)kd, (float)cd);
+    if (r == 1) tally_track(O, f, (float)kd);
   }
 }
 
@@ -818,44 +883,82 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
 __global__ void __launch_bounds__(256)
 k_vcand(int F, Consts C, uint32_t* __restrict__ flags, const int32_t* __restrict__ counts,
         const int32_t* __restrict__ ccnt, int32_t* __restrict__ vbase, int32_t* __restrict__ vpos,
-        int32_t* __restrict__ cand, int32_t* __restrict__ counters) {
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < F; f += gridDim.x * blockDim.x) {
-    vbase[f] = -1;
-    const uint32_t fl = flags[f];
-    if (fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF)) continue;
-    const int nt = counts[3 * f + 1];
-    if (nt > C.max_trk) { flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP; continue; }
-    const int cc = ccnt[f];
-    if ((cc & 0xffff) < 2 || (cc >> 16) < 1) continue;
-    const int c = atomicAdd(&counters[3], 1);
-    vbase[f] = atomicAdd(&counters[4], nt);
-    vpos[f] = 0;
-    cand[c] = f;
+        int32_t* __restrict__ cand, int vcap, int32_t* __restrict__ counters) {
+  // one thread per frame; candidate slots and table slices are reserved with
+  // one atomic per wave (ballot rank and a wave prefix sum of track counts)
+  const int lane = threadIdx.x & 63;
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < F; base += stride) {
+    const int f = base + lane;
+    int nt = 0;
+    bool is_cand = false;
+    if (f < F) {
+      vbase[f] = -1;
+      const uint32_t fl = flags[f];
+      if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF))) {
+        nt = counts[3 * f + 1];
+        if (nt > C.max_trk) {
+          flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP;
+        } else {
+          const int cc = ccnt[f];
+          is_cand = (cc & 0xffff) >= 2 && (cc >> 16) >= 1;
+        }
+      }
+    }
+    const unsigned long long bm = __ballot(is_cand);
+    if (bm == 0ull) continue;   // wave-uniform
+    int incl = is_cand ? nt : 0;   // inclusive prefix sum of candidate track counts
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    int c0 = 0, t0 = 0;
+    if (lane == 0) {
+      c0 = atomicAdd(&counters[3], __popcll(bm));
+      t0 = atomicAdd(&counters[4], total);
+      if (t0 + total > vcap) atomicOr(&counters[2], ST_TRACK_FULL);
+    }
+    c0 = __shfl(c0, 0, 64);
+    t0 = __shfl(t0, 0, 64);
+    if (is_cand) {
+      vbase[f] = t0 + incl - nt;
+      vpos[f] = 0;
+      cand[c0 + __popcll(bm & lanemask_lt())] = f;
+    }
   }
 }
 
-// Float64 vertex-stage quantities of the tracks of candidate frames, and the
-// frames' track tables.
-__global__ void __launch_bounds__(256)
-k_vprep_list(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits, Consts C,
-             const int32_t* __restrict__ trk, int trk_cap, const int32_t* __restrict__ counters,
-             const int32_t* __restrict__ vbase, int32_t* __restrict__ vpos, int32_t* __restrict__ ctab,
-             VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
-  const int n = min(counters[1], trk_cap);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int f = trk[8 * t];
+// Float64 vertex-stage quantities of the accepted tracks of candidate
+// frames, placed in the frames' slices of the candidate table (vt, vok); one
+// wave per 64-entry slice of the triplet list.
+__global__ void __launch_bounds__(64)
+k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
+        const int32_t* __restrict__ lo, Consts C, TripList T, Slices S, const int32_t* __restrict__ res,
+        const int32_t* __restrict__ counters, const int32_t* __restrict__ vbase, int32_t* __restrict__ vpos, int vcap,
+        VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
+  const int ns = counters[10];
+  for (int v = blockIdx.x; v < ns; v += gridDim.x) {
+    const int pkd = S.all[v];
+    const int32_t* row = T.chunks + 4 * (pkd / kWave);
+    const int start = row[0], n = row[1];
+    const int t = (pkd % kWave) * kWave + (int)threadIdx.x;
+    if (t >= n) continue;
+    const int e = start + t;
+    if (res[4 * e] != TR_ACCEPT) continue;
+    const int f = T.trips[2 * e];
     const int b = vbase[f];
     if (b < 0) continue;
-    vok[t] = vtrack_make(X, Y, Z, n_hits, trk + 8 * t + 1, C, vt[t]) ? 1 : 0;
     const int pos = atomicAdd(&vpos[f], 1);
-    if (b + pos < trk_cap) ctab[b + pos] = t;
+    if (b + pos >= vcap) continue;   // table full: reported by k_vcand
+    const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
+    const int32_t h[4] = {lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
+                          lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3] + res[4 * e + 1]};
+    vok[b + pos] = vtrack_make(X, Y, Z, n_hits, h, C, vt[b + pos]) ? 1 : 0;
   }
 }
 
-struct TableId {
-  const int32_t* tab; int base;
-  __device__ int operator()(int j) const { return tab[base + j]; }
-};
 struct RangeId {
   int base;
   __device__ int operator()(int j) const { return base + j; }
@@ -863,16 +966,15 @@ struct RangeId {
 
 __global__ void __launch_bounds__(64)
 k_vframes_list(Consts C, const int32_t* __restrict__ counters, const int32_t* __restrict__ cand,
-               const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos,
-               const int32_t* __restrict__ ctab, int trk_cap, const VTrack* __restrict__ vt,
-               const int32_t* __restrict__ vok, uint32_t* __restrict__ flags, int32_t* __restrict__ counts,
-               float* __restrict__ vtx) {
+               const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos, int vcap,
+               const VTrack* __restrict__ vt, const int32_t* __restrict__ vok, uint32_t* __restrict__ flags,
+               int32_t* __restrict__ counts, float* __restrict__ vtx) {
   const int nc = counters[3];
   for (int c = blockIdx.x; c < nc; c += gridDim.x) {
     const int f = cand[c];
     const int b = vbase[f], n = vpos[f];
-    if (b < 0 || b + n > trk_cap) continue;   // track list overflowed: reported in the status word
-    vertex_wave(f, n, TableId{ctab, b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
+    if (b < 0 || b + n > vcap) continue;   // table full: reported in the status word
+    vertex_wave(f, n, RangeId{b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
   }
 }
 
@@ -992,8 +1094,11 @@ __global__ void k_zero(int32_t* __restrict__ p, int n) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters, chunks, trips, trk, redo, vt, vok, ctab, ccnt, vbase, vpos, cand, total;
+  size_t counters, chunks, trips, res, sfit, sall, redo, vt, vok, ccnt, vbase, vpos, cand, total;
 };
+
+// Entries of each slice table: at most ceil(count / 64) slices per chunk.
+inline int64_t slice_capacity(int64_t tc) { return tc / kWave + tc / kMinChunk + 2; }
 
 Layout layout(int64_t F, int64_t tc, int64_t kc) {
   Layout L;
@@ -1001,11 +1106,12 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.counters = o; o += align256(kCounters * sizeof(int32_t));
   L.chunks = o; o += align256((size_t)(tc / kMinChunk + 1) * 4 * sizeof(int32_t));
   L.trips = o; o += align256((size_t)tc * 2 * sizeof(int32_t));
-  L.trk = o; o += align256((size_t)kc * 8 * sizeof(int32_t));
-  L.redo = o; o += align256((size_t)(kc / 8 + 1024) * 2 * sizeof(int32_t));
+  L.res = o; o += align256((size_t)tc * 4 * sizeof(int32_t));
+  L.sfit = o; o += align256((size_t)slice_capacity(tc) * sizeof(int32_t));
+  L.sall = o; o += align256((size_t)slice_capacity(tc) * sizeof(int32_t));
+  L.redo = o; o += align256((size_t)(kc / 8 + 1024) * sizeof(int32_t));
   L.vt = o; o += align256((size_t)kc * sizeof(VTrack));
   L.vok = o; o += align256((size_t)kc * sizeof(int32_t));
-  L.ctab = o; o += align256((size_t)kc * sizeof(int32_t));
   L.ccnt = o; o += align256((size_t)F * sizeof(int32_t));
   L.vbase = o; o += align256((size_t)F * sizeof(int32_t));
   L.vpos = o; o += align256((size_t)F * sizeof(int32_t));
@@ -1050,7 +1156,8 @@ int device_cus() {
 
 // Pointers into a caller workspace.
 struct WsView {
-  int32_t *counters, *chunks, *trips, *trk, *redo, *ctab, *ccnt, *vbase, *vpos, *cand, *vok;
+  int32_t *counters, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok;
+  Slices S;
   VTrack* vt;
   int redo_cap;
 };
@@ -1061,17 +1168,28 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.counters = reinterpret_cast<int32_t*>(ws + L.counters);
   W.chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
   W.trips = reinterpret_cast<int32_t*>(ws + L.trips);
-  W.trk = reinterpret_cast<int32_t*>(ws + L.trk);
+  W.res = reinterpret_cast<int32_t*>(ws + L.res);
+  W.S.fit = reinterpret_cast<int32_t*>(ws + L.sfit);
+  W.S.all = reinterpret_cast<int32_t*>(ws + L.sall);
   W.redo = reinterpret_cast<int32_t*>(ws + L.redo);
   W.vt = reinterpret_cast<VTrack*>(ws + L.vt);
   W.vok = reinterpret_cast<int32_t*>(ws + L.vok);
-  W.ctab = reinterpret_cast<int32_t*>(ws + L.ctab);
   W.ccnt = reinterpret_cast<int32_t*>(ws + L.ccnt);
   W.vbase = reinterpret_cast<int32_t*>(ws + L.vbase);
   W.vpos = reinterpret_cast<int32_t*>(ws + L.vpos);
   W.cand = reinterpret_cast<int32_t*>(ws + L.cand);
   W.redo_cap = track_capacity / 8 + 1024;
   return W;
+}
+
+TrackOut track_out(const WsView& W, int32_t* counts) {
+  TrackOut O;
+  O.res = W.res;
+  O.redo = W.redo;
+  O.redo_cap = W.redo_cap;
+  O.counts = counts;
+  O.ccnt = W.ccnt;
+  return O;
 }
 
 // The triplet list of a launch with `waves` appending waves: chunks of about
@@ -1089,17 +1207,32 @@ TripList trip_list(const WsView& W, int capacity, int waves) {
   return T;
 }
 
-// Vertex stage (Alg. 4) after the track stage of either form.
-void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const WsView& W, uint32_t* flags,
-                   int32_t* counts, float* vtx, int track_capacity, hipStream_t stream, hipEvent_t* ev) {
+// Track stage after the cuts of either form: slice tables, float32 fits of
+// the entries not fitted yet, float64 re-evaluation.  after_fits (nullable)
+// is recorded after k_tracks.
+void launch_tracks(const mu3e_hits_t& h, const Consts& C, int cus, const WsView& W, const TripList& T,
+                   const uint32_t* flags, int32_t* counts, hipStream_t stream, hipEvent_t after_fits) {
+  const TrackOut O = track_out(W, counts);
+  hipLaunchKernelGGL(k_slices, dim3(1), dim3(1024), 0, stream, T, W.S, W.counters);
+  hipLaunchKernelGGL(k_tracks, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, flags, T,
+                     W.S, O, W.counters);
+  if (after_fits) (void)hipEventRecord(after_fits, stream);
+  hipLaunchKernelGGL(k_tracks_redo, dim3(cus), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, T, O,
+                     W.counters);
+}
+
+// Vertex stage (Alg. 4) after the track stage of either form; vcap is the
+// capacity of the candidate track table.
+void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const WsView& W, const TripList& T,
+                   uint32_t* flags, int32_t* counts, float* vtx, int vcap, hipStream_t stream, hipEvent_t* ev) {
   const int gf = (F + 255) / 256 < cus * 8 ? (F + 255) / 256 : cus * 8;
   hipLaunchKernelGGL(k_vcand, dim3(gf), dim3(256), 0, stream, F, C, flags, counts, W.ccnt, W.vbase, W.vpos, W.cand,
-                     W.counters);
-  hipLaunchKernelGGL(k_vprep_list, dim3(cus * 4), dim3(256), 0, stream, h.x, h.y, h.z, h.n_hits, C, W.trk,
-                     track_capacity, W.counters, W.vbase, W.vpos, W.ctab, W.vt, W.vok);
+                     vcap, W.counters);
+  hipLaunchKernelGGL(k_vprep, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets, C, T,
+                     W.S, W.res, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok);
   if (ev) (void)hipEventRecord(ev[3], stream);
   hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, C, W.counters, W.cand, W.vbase, W.vpos,
-                     W.ctab, track_capacity, W.vt, W.vok, flags, counts, vtx);
+                     vcap, W.vt, W.vok, flags, counts, vtx);
   if (ev) (void)hipEventRecord(ev[4], stream);
 }
 
@@ -1151,7 +1284,7 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
   if (g1 > F) g1 = F > 0 ? F : 1;
   const TripList T = trip_list(W, triplet_capacity, g1);
   if (dbg) {
-    dbg->counters = W.counters; dbg->triplets = W.trips; dbg->tracks = W.trk;
+    dbg->counters = W.counters; dbg->triplets = W.trips; dbg->tracks = W.res;
     dbg->triplet_capacity = triplet_capacity; dbg->track_capacity = track_capacity;
     dbg->chunks = W.chunks; dbg->max_chunks = triplet_capacity / kMinChunk + 1; dbg->chunk_size = T.chunk;
   }
@@ -1164,13 +1297,9 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
   hipLaunchKernelGGL(k_cuts, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, F,
                      hits->n_hits, C, frame_flags, frame_counts, frame_vertex, W.ccnt, T, W.counters);
   if (ev) (void)hipEventRecord(ev[1], stream);
-  hipLaunchKernelGGL(k_tracks, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, C,
-                     frame_flags, T, frame_counts, W.ccnt, W.trk, track_capacity, W.redo, W.redo_cap, W.counters);
-  hipLaunchKernelGGL(k_tracks_redo, dim3(cus), dim3(kWave), 0, stream, hits->x, hits->y, hits->z,
-                     hits->layer_offsets, C, W.redo, W.redo_cap, frame_counts, W.ccnt, W.trk, track_capacity,
-                     W.counters);
+  launch_tracks(*hits, C, cus, W, T, frame_flags, frame_counts, stream, nullptr);
   if (ev) (void)hipEventRecord(ev[2], stream);
-  launch_vertex(*hits, C, F, cus, W, frame_flags, frame_counts, frame_vertex, track_capacity, stream, ev);
+  launch_vertex(*hits, C, F, cus, W, T, frame_flags, frame_counts, frame_vertex, track_capacity, stream, ev);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
@@ -1292,25 +1421,22 @@ struct mu3e_plan {
 // events): before and after the persistent kernel, after k_tracks, at the end.
 static void plan_launch(const mu3e_plan& pl, hipStream_t s, hipEvent_t* ev) {
   const mu3e_hits_t& h = pl.hits;
+  const TrackOut O = track_out(pl.W, pl.counts);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, pl.W.counters, kCounters);
   if (pl.F == 0) return;
   if (ev) (void)hipEventRecord(ev[0], s);
   if (pl.tuning.fuse_fits)
     hipLaunchKernelGGL(k_batched<true>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits,
-                       pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, pl.W.trk, pl.kcap, pl.W.redo,
-                       pl.W.redo_cap, pl.W.counters, pl.tuning.frames_per_claim);
+                       pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
+                       pl.tuning.frames_per_claim);
   else
-    hipLaunchKernelGGL(k_batched<false>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits,
-                       pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, pl.W.trk, pl.kcap, pl.W.redo,
-                       pl.W.redo_cap, pl.W.counters, pl.tuning.frames_per_claim);
+    hipLaunchKernelGGL(k_batched<false>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F,
+                       h.n_hits, pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
+                       pl.tuning.frames_per_claim);
   if (ev) (void)hipEventRecord(ev[1], s);
   // fits left by the persistent kernel (all of them without fusion)
-  hipLaunchKernelGGL(k_tracks, dim3(pl.cus * 16), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.flags, pl.T,
-                     pl.counts, pl.W.ccnt, pl.W.trk, pl.kcap, pl.W.redo, pl.W.redo_cap, pl.W.counters);
-  if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL(k_tracks_redo, dim3(pl.cus), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.C, pl.W.redo,
-                     pl.W.redo_cap, pl.counts, pl.W.ccnt, pl.W.trk, pl.kcap, pl.W.counters);
-  launch_vertex(h, pl.C, pl.F, pl.cus, pl.W, pl.flags, pl.counts, pl.vertex, pl.kcap, s, nullptr);
+  launch_tracks(h, pl.C, pl.cus, pl.W, pl.T, pl.flags, pl.counts, s, ev ? ev[2] : nullptr);
+  launch_vertex(h, pl.C, pl.F, pl.cus, pl.W, pl.T, pl.flags, pl.counts, pl.vertex, pl.kcap, s, nullptr);
   if (ev) (void)hipEventRecord(ev[3], s);
 }
 
@@ -1347,7 +1473,7 @@ mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const m
   mu3e_plan* pl = new (std::nothrow) mu3e_plan;
   if (!pl) return MU3E_ERR_CAPACITY;
   pl->tuning = t;
-  pl->dbg.counters = W.counters; pl->dbg.triplets = W.trips; pl->dbg.tracks = W.trk;
+  pl->dbg.counters = W.counters; pl->dbg.triplets = W.trips; pl->dbg.tracks = W.res;
   pl->dbg.triplet_capacity = triplet_capacity; pl->dbg.track_capacity = track_capacity;
   pl->hits = *hits; pl->C = C; pl->W = W;
   pl->flags = frame_flags; pl->counts = frame_counts; pl->vertex = frame_vertex;

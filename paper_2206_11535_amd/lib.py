@@ -228,19 +228,20 @@ class Selector:
         _check(st, "mu3e_select_frames")
 
     def counters(self):
-        """[triplets selected, tracks appended, status bits, ..., triplet
-        entries handed out in chunks at index 7, ...] (synchronises)."""
+        """Device counters (synchronises): [0] triplets selected, [2] status
+        bits, [7] triplet entries handed out in chunks, ..."""
         import torch
-        n = 9
+        n = 11
         base = self.dbg.counters - self.ws.data_ptr()
         return self.ws[base:base + 4 * n].view(torch.int32).cpu().numpy()
 
     def lists(self, hits_offsets: np.ndarray):
-        """Host copies of the triplet and track lists (global hit indices);
-        triplets of frames flagged TRIPLET_OVF are left out."""
+        """Host copies of the selected triplets and the accepted tracks
+        (global hit indices); triplets of frames flagged TRIPLET_OVF are left
+        out.  Returns (triplets [n, 4]: frame, h0, h1, h2; tracks [m, 5]:
+        frame, h0..h3; kf [m, 2]: kappa_bar, chi2; counters)."""
         import torch
         c = self.counters()
-        nk = min(int(c[1]), self.kcap)
         ws = self.ws
         d = self.dbg
         nch = min(int(c[7]), d.triplet_capacity) // d.chunk_size if d.chunk_size > 0 else 0
@@ -248,20 +249,23 @@ class Selector:
         ch = ws[cb:cb + 16 * nch].view(torch.int32).cpu().numpy().reshape(-1, 4)
         tb = d.triplets - ws.data_ptr()
         allt = ws[tb:tb + 8 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 2)
-        trips = np.concatenate([allt[a:a + n] for a, n in ch[:, :2]]) if nch else np.zeros((0, 2), np.int32)
+        rb = d.tracks - ws.data_ptr()
+        allr = ws[rb:rb + 16 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 4)
+        idx = np.concatenate([np.arange(a, a + n) for a, n in ch[:, :2]]) if nch else np.zeros(0, np.int64)
+        trips = allt[idx]
+        res = allr[idx]
         flags = self.flags[:self.n_frames].cpu().numpy().view(np.uint32)
-        if len(trips):
-            trips = trips[(flags[trips[:, 0]] & TRIPLET_OVF) == 0]
-        kb = d.tracks - ws.data_ptr()
-        trk = ws[kb:kb + 32 * nk].view(torch.int32).cpu().numpy().reshape(-1, 8)
+        keep = (flags[trips[:, 0]] & TRIPLET_OVF) == 0 if len(trips) else np.zeros(0, bool)
+        trips, res = trips[keep], res[keep]
         lo = np.asarray(hits_offsets)
         f = trips[:, 0].astype(np.int64)
         pk = trips[:, 1].astype(np.int64)
         g = np.stack([lo[4 * f] + (pk & 0xff), lo[4 * f + 1] + ((pk >> 8) & 0xff),
                       lo[4 * f + 2] + ((pk >> 16) & 0xff)], 1)
         triplets = np.concatenate([f[:, None], g], 1)
-        tracks = trk[:, [0, 1, 2, 3, 4]].astype(np.int64)
-        kf = trk[:, 6:8].copy().view(np.float32)
+        acc = res[:, 0] == 1
+        tracks = np.concatenate([triplets[acc], (lo[4 * f[acc] + 3] + res[acc, 1])[:, None]], 1)
+        kf = res[acc, 2:4].copy().view(np.float32)
         return triplets, tracks, kf, c
 
     def result(self):
