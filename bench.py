@@ -230,8 +230,9 @@ def main():
     ms_plain, stage_ms, _ = time_steps(plain, dh, stream, hip, a.steps, a.warmup, staged=True)
     fitted, flops, flags = fitted_triplets(plain, fs)
     # ---- batched form (autotuned shape, cached)
-    (w, c, u), _, _ = autotune.tune(dh, p)
-    batched = lib.BatchedSelector(dh, p, device=dev, waves_per_cu=w, frames_per_claim=c, fuse_fits=u)
+    (w, c, u, st), _, _ = autotune.tune(dh, p)
+    batched = lib.BatchedSelector(dh, p, device=dev, waves_per_cu=w, frames_per_claim=c, fuse_fits=u,
+                                  steal_percent=st)
     ms_batched, _, wall = time_steps(batched, dh, stream, hip, a.steps, a.warmup)
     identical = same_outputs(plain, batched)
     # kernel durations: the same sequence launched eagerly with events around
@@ -270,7 +271,7 @@ def main():
         "config": {"workload": f"nominal rate, {F} frames of 64 ns, Poisson(6.4) Michel decays + 5 noise "
                                f"hits/layer, signal in 1% of frames", "frames": F, "form": "batched",
                    "waves_per_cu": batched.effective[0], "frames_per_claim": batched.effective[1],
-                   "fused_fits": fused},
+                   "fused_fits": fused, "steal_percent": batched.effective[3]},
         "fitted_triplets_per_s": fitted / (ms_batched / 1e3),
         "plain": {"value": F / (ms_plain / 1e3), "ms_per_step": ms_plain,
                   "fitted_triplets_per_s": fitted / (ms_plain / 1e3),
@@ -291,15 +292,16 @@ def main():
         dm = lib.to_device(fm, dev)
         sp = lib.Selector(fm.n_frames, p, device=dev)
         msp, _, _ = time_steps(sp, dm, stream, hip, max(3, a.steps // 4), 1)
-        (wm, cm, um), _, _ = autotune.tune(dm, p)
-        sb = lib.BatchedSelector(dm, p, device=dev, waves_per_cu=wm, frames_per_claim=cm, fuse_fits=um)
+        (wm, cm, um, sm), _, _ = autotune.tune(dm, p)
+        sb = lib.BatchedSelector(dm, p, device=dev, waves_per_cu=wm, frames_per_claim=cm, fuse_fits=um,
+                                 steal_percent=sm)
         msb, _, _ = time_steps(sb, dm, stream, hip, max(3, a.steps // 4), 1)
         out["mixed"] = {"workload": f"{fm.n_frames} frames, lambda per frame from {{2, 6.4, 12, 20}}",
                         "plain_frames_per_s": fm.n_frames / (msp / 1e3),
                         "batched_frames_per_s": fm.n_frames / (msb / 1e3),
                         "batched_equals_plain": same_outputs(sp, sb),
                         "waves_per_cu": sb.effective[0], "frames_per_claim": sb.effective[1],
-                        "fused_fits": bool(sb.effective[2])}
+                        "fused_fits": bool(sb.effective[2]), "steal_percent": sb.effective[3]}
         del sp, sb, dm
     if a.align:
         fa = synth.generate(synth.CONFIGS[5])

@@ -212,9 +212,10 @@ mu3e_status mu3e_vertex(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
 
 /* ---- Batched form ------------------------------------------------------
  * A plan captures the whole selection of one batch of frames into a HIP
- * graph around one persistent kernel: waves claim frames_per_claim frames at
- * a time from a shared counter (work stealing over uneven frames) and run
- * the Selection Cuts of each frame; with fuse_fits the same waves also fit
+ * graph around one persistent kernel: waves take the frames of the batch
+ * cyclically, except a tail of steal_percent % of them which they claim
+ * frames_per_claim frames at a time from shared counters (work stealing over
+ * uneven frames), and run the Selection Cuts of each frame; with fuse_fits the same waves also fit
  * the pending survivors of their frames 64 at a time, otherwise a fit kernel
  * follows in the graph.  The float64 re-evaluation and the vertex stage
  * follow in the same graph.  Outputs are identical to mu3e_select_frames.
@@ -228,6 +229,9 @@ typedef struct {
                                  capped by occupancy)                           */
   int32_t frames_per_claim;   /* frames taken per work-stealing claim (0: 4)   */
   int32_t fuse_fits;          /* 1: the persistent waves also fit (see above)  */
+  int32_t steal_percent;      /* 0..100: share of the frames (the tail of the
+                                 batch) taken by work stealing; the rest is
+                                 dealt cyclically                              */
 } mu3e_tuning_t;
 
 /* Workspace as mu3e_select_workspace_size.  tuning may be NULL.  Allocates

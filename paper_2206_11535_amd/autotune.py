@@ -1,5 +1,6 @@
-"""Autotuner of the batched form: persistent waves per compute unit, frames
-per work-stealing claim, and whether the persistent waves also fit.
+"""Autotuner of the batched form: persistent waves per compute unit, the
+share of frames taken by work stealing, frames per claim, and whether the
+persistent waves also fit.
 
 Each candidate plan runs the given workload (already resident on the GPU);
 its mean step time over event-timed repeats is measured and the fastest
@@ -19,8 +20,19 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(PKG, "tuning_cache.json")
 
 WAVES_PER_CU = (4, 8, 12, 16, 20, 24, 32)
-FRAMES_PER_CLAIM = (1, 2, 4, 8, 16, 32)
 FUSE_FITS = (0, 1)
+STEAL_PERCENT = (12, 25, 50)
+STEAL_WAVES_PER_CU = (8, 12, 16)
+FRAMES_PER_CLAIM = (4, 8, 16, 32)
+
+
+def candidates():
+    """(waves_per_cu, frames_per_claim, fuse_fits, steal_percent) shapes: the
+    purely cyclic schedule at every wave count, and stealing tails."""
+    out = [(w, 0, u, 0) for u in FUSE_FITS for w in WAVES_PER_CU]
+    out += [(w, c, u, st) for u in FUSE_FITS for st in STEAL_PERCENT for w in STEAL_WAVES_PER_CU
+            for c in FRAMES_PER_CLAIM]
+    return out
 
 
 def source_tag() -> str:
@@ -60,8 +72,8 @@ def time_plan(sel, reps: int = 5, warmup: int = 2) -> float:
 
 
 def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: int = 5,
-         candidates=None, use_cache: bool = True, verbose: bool = False):
-    """Return ((waves_per_cu, frames_per_claim, fuse_fits), ms, table)."""
+         candidates_=None, use_cache: bool = True, verbose: bool = False):
+    """Return ((waves_per_cu, frames_per_claim, fuse_fits, steal_percent), ms, table)."""
     import torch
     from . import lib
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
@@ -69,13 +81,12 @@ def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: i
     cache = load_cache()
     if use_cache and key in cache:
         e = cache[key]
-        return (e["waves_per_cu"], e["frames_per_claim"], e["fuse_fits"]), e["ms"], None
-    cand = candidates or [(w, c, u) for u in FUSE_FITS for w in WAVES_PER_CU for c in FRAMES_PER_CLAIM]
+        return (e["waves_per_cu"], e["frames_per_claim"], e["fuse_fits"], e["steal_percent"]), e["ms"], None
     table = []
     seen = set()
-    for w, c, u in cand:
+    for w, c, u, st in candidates_ or candidates():
         sel = lib.BatchedSelector(hits, params, triplet_capacity, track_capacity, waves_per_cu=w,
-                                  frames_per_claim=c, fuse_fits=u)
+                                  frames_per_claim=c, fuse_fits=u, steal_percent=st)
         if sel.effective in seen:          # capped by occupancy: same shape as before
             del sel
             continue
@@ -83,11 +94,13 @@ def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: i
         ms = time_plan(sel, reps)
         table.append((*sel.effective, ms))
         if verbose:
-            print(f"  waves/CU {sel.effective[0]:3d} frames/claim {sel.effective[1]:3d} fused {sel.effective[2]}: "
-                  f"{ms:.4f} ms", flush=True)
+            e = sel.effective
+            print(f"  waves/CU {e[0]:3d} frames/claim {e[1]:3d} fused {e[2]} steal {e[3]:3d}%: {ms:.4f} ms",
+                  flush=True)
         del sel
-    best = min(table, key=lambda r: r[3])
-    cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "fuse_fits": best[2], "ms": best[3]}
+    best = min(table, key=lambda r: r[4])
+    cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "fuse_fits": best[2],
+                  "steal_percent": best[3], "ms": best[4]}
     with open(CACHE, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
-    return (best[0], best[1], best[2]), best[3], table
+    return tuple(best[:4]), best[4], table

@@ -39,12 +39,12 @@ constexpr int kCounters = 64;                // int32 counters at the workspace 
 constexpr int kMinChunk = 64;                // triplet-list chunk sizes lie in [64, 4096]
 constexpr int kMaxChunk = 4096;
 constexpr int kMaxTripletCapacity = 1 << 30; // keeps the chunk bump counter within int32
-constexpr int kClaimRanges = 8;              // claim counters of the batched form
+constexpr int kClaimRanges = 8;              // claim counters of the batched form,
+constexpr int kClaimStride = 1024;           // int32 apart (4 KiB)
 
 // counters: [0] triplets selected, [2] status bits, [3] candidate frames of
 // the vertex stage, [4] their track-table size, [5] entries queued for the
-// float64 re-evaluation, [16 .. 23] frame claim counters of the batched
-// form, [7] triplet-list entries handed out in chunks (also past the capacity:
+// float64 re-evaluation, [7] triplet-list entries handed out in chunks (also past the capacity:
 // each grant adds one chunk), [9] and [10] lengths of the slice tables
 enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
 
@@ -174,6 +174,34 @@ struct CutLds {
   uint32_t spend[2 * kWave];
 };
 
+// ------------------------------------------------------------ frame loads
+// What a wave needs of a frame before its cuts, held in registers so that it
+// can be loaded while the previous frame is processed: lanes 0..4 hold
+// layer_offsets[4f .. 4f+4], lane i < 64 holds hit i of layers 0..2 (x, y, z).
+struct FrameRegs {
+  int lo;
+  float x, y, z;
+};
+
+__device__ inline int load_offsets(const int32_t* __restrict__ lo, int f, bool valid) {
+  const int lane = threadIdx.x;
+  return valid && lane < 5 ? lo[4 * f + lane] : 0;
+}
+
+// Issues the hit loads of a frame whose offsets are in R.lo; only indices
+// inside [b0, b3) and [0, n_hits) are read (malformed offsets read nothing).
+__device__ inline void load_hits(FrameRegs& R, const float* __restrict__ X, const float* __restrict__ Y,
+                                 const float* __restrict__ Z, int n_hits, bool valid) {
+  const int b0 = __shfl(R.lo, 0, 64), b3 = __shfl(R.lo, 3, 64);
+  const int i = b0 + (int)threadIdx.x;
+  R.x = R.y = R.z = 0.f;
+  if (valid && b0 >= 0 && i < b3 && i < n_hits) {
+    R.x = X[i];
+    R.y = Y[i];
+    R.z = Z[i];
+  }
+}
+
 // Selection Cuts of frame f by one wave (Alg. 2): the frame's layer-0..2
 // hits are staged in LDS; a 128-bit mask of layer-0 partners passing Phi01
 // per layer-1 hit; (h1, h2) pairs passing Phi12 are streamed through an LDS
@@ -183,13 +211,14 @@ struct CutLds {
 // its current chunk, recorded when the chunk is closed); returns the number
 // committed (0 when the frame overflows max_triplets) and writes the frame's
 // flags and counts.
-__device__ int cut_frame(int f, const float* __restrict__ X, const float* __restrict__ Y,
-                         const float* __restrict__ Z, const int32_t* __restrict__ lo, int n_hits, const Consts& C,
+__device__ __attribute__((always_inline)) inline int cut_frame(int f, const FrameRegs& R, const float* __restrict__ X, const float* __restrict__ Y,
+                         const float* __restrict__ Z, int n_hits, const Consts& C,
                          CutLds& L, const TripList& T, Cursor& cur, int& done,
                          uint32_t* __restrict__ flags, int32_t* __restrict__ counts, float* __restrict__ vtx,
                          int32_t* __restrict__ ccnt, int32_t* __restrict__ counters) {
   const int lane = threadIdx.x;
-  const int b0 = lo[4 * f], b1 = lo[4 * f + 1], b2 = lo[4 * f + 2], b3 = lo[4 * f + 3], b4 = lo[4 * f + 4];
+  const int b0 = __shfl(R.lo, 0, 64), b1 = __shfl(R.lo, 1, 64), b2 = __shfl(R.lo, 2, 64);
+  const int b3 = __shfl(R.lo, 3, 64), b4 = __shfl(R.lo, 4, 64);
   const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2, n3 = b4 - b3;
   if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
   if (lane == 0) { ccnt[f] = 0; counts[3 * f + 1] = 0; counts[3 * f + 2] = 0; }
@@ -207,9 +236,10 @@ __device__ int cut_frame(int f, const float* __restrict__ X, const float* __rest
   for (int i = lane; i < n012; i += kWave) {
     const int l = (i >= n0) + (i >= n0 + n1);
     const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
-    L.sx[l * kMaxLayerHits + k] = X[b0 + i];
-    L.sy[l * kMaxLayerHits + k] = Y[b0 + i];
-    L.sz[l * kMaxLayerHits + k] = Z[b0 + i];
+    const bool pre = i < kWave;   // hits 0..63 arrive prefetched in registers
+    L.sx[l * kMaxLayerHits + k] = pre ? R.x : X[b0 + i];
+    L.sy[l * kMaxLayerHits + k] = pre ? R.y : Y[b0 + i];
+    L.sz[l * kMaxLayerHits + k] = pre ? R.z : Z[b0 + i];
   }
   for (int i = lane; i < 2 * n1; i += kWave) L.sm01[i] = 0ull;
   __syncthreads();
@@ -315,6 +345,33 @@ __device__ inline void close_list(const Cursor& cur, int done, int selected, con
   if (threadIdx.x == 0 && selected > 0) atomicAdd(&counters[0], selected);
 }
 
+// Runs body(f, regs) for the frames first, next(first), ... (next returns -1
+// after the last; all wave-uniform), loading each frame's offsets two frames
+// ahead and its hits one frame ahead, so that the loads overlap the cuts of
+// the frame before.
+template <class Next, class Body>
+__device__ inline void frame_pipeline(int first, Next next, Body body, const int32_t* __restrict__ lo,
+                                      const float* __restrict__ X, const float* __restrict__ Y,
+                                      const float* __restrict__ Z, int n_hits) {
+  int f = first;
+  FrameRegs cur;
+  cur.lo = load_offsets(lo, f, f >= 0);
+  load_hits(cur, X, Y, Z, n_hits, f >= 0);
+  int f1 = f >= 0 ? next(f) : -1;
+  int nlo = load_offsets(lo, f1, f1 >= 0);
+  while (f >= 0) {
+    const int f2 = f1 >= 0 ? next(f1) : -1;
+    FrameRegs nx;
+    nx.lo = nlo;
+    load_hits(nx, X, Y, Z, n_hits, f1 >= 0);
+    nlo = load_offsets(lo, f2, f2 >= 0);
+    body(f, cur);
+    cur = nx;
+    f = f1;
+    f1 = f2;
+  }
+}
+
 // Plain form: one wave per frame, frames dealt cyclically to a static grid
 // (Alg. 1 with the paper's cyclic distribution); survivors go to the wave's
 // chunks of the triplet list.
@@ -326,8 +383,13 @@ k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __
   __shared__ CutLds L;
   Cursor cur = cursor_init();
   int done = 0, selected = 0;   // nothing is fitted here
-  for (int f = blockIdx.x; f < F; f += gridDim.x)
-    selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+  const int G = gridDim.x;
+  frame_pipeline(
+      (int)blockIdx.x < F ? (int)blockIdx.x : -1, [&](int g) { return g < F - G ? g + G : -1; },
+      [&](int f, const FrameRegs& R) {
+        selected += cut_frame(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+      },
+      lo, X, Y, Z, n_hits);
   close_list(cur, 0, selected, T, counters);
 }
 
@@ -524,20 +586,23 @@ k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* 
 }
 
 // ============================================================ batched form
-// Persistent waves claim `claim` frames at a time from shared counters (work
-// stealing over uneven frames) and run the Selection Cuts of each frame.
-// kFuse: the same wave also fits the pending survivors of its frames 64 at a
-// time (fit batches span frames); entries left unfitted in a chunk closed in
-// the middle of a frame are recorded for k_tracks.  Without kFuse the kernel
-// needs far fewer registers (more resident waves for the latency-bound cuts)
-// and k_tracks fits everything.  Undecided fits go to the float64 list as in
-// the plain form.
+// Persistent waves run the Selection Cuts of all frames: frames [0, Fs) are
+// dealt cyclically to the waves (the paper's scheme, no shared counters),
+// and the tail [Fs, F) is taken by work stealing -- `claim` frames at a time
+// from kClaimRanges counters over kClaimRanges sub-ranges of the tail, each
+// counter on its own 4-KiB line (claims spread over memory channels); a wave
+// starts in sub-range blockIdx mod kClaimRanges and moves on when it is used
+// up.  kFuse: the same wave also fits the pending survivors of its frames 64
+// at a time (fit batches span frames); entries left unfitted in a chunk
+// closed in the middle of a frame are recorded for k_tracks.  Without kFuse
+// the kernel needs far fewer registers (more resident waves for the
+// latency-bound cuts) and k_tracks fits everything.
 template <bool kFuse>
 __global__ void __launch_bounds__(64)
 k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
-          const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
+          const int32_t* __restrict__ lo, int F, int Fs, int n_hits, Consts C, uint32_t* __restrict__ flags,
           int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
-          TrackOut O, int32_t* __restrict__ counters, int claim) {
+          TrackOut O, int32_t* __restrict__ counters, int32_t* __restrict__ claims, int claim) {
   __shared__ CutLds L;
   const int lane = threadIdx.x;
   Cursor cur = cursor_init();
@@ -554,30 +619,45 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
     emit_result(active, r, e, f, i3, kb, c2, O, counters);
     done += k;
   };
-  // The frames are split into kClaimRanges ranges with a claim counter each
-  // (counters[16 + k]), so that claims spread over several addresses; a wave
-  // starts in range blockIdx.x % kClaimRanges and moves on when it is used up.
-  for (int i = 0; i < kClaimRanges; ++i) {
-    const int k = (int)((blockIdx.x + i) % kClaimRanges);
-    const int r0 = (int)((int64_t)F * k / kClaimRanges), r1 = (int)((int64_t)F * (k + 1) / kClaimRanges);
-    int32_t* ctr = &counters[16 + k];
-    for (;;) {
+  auto body = [&](int f, const FrameRegs& R) {
+    selected += cut_frame(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+    if constexpr (kFuse) {
+      while (cur.used - done >= kWave) fit(kWave);
+    }
+  };
+  // Frame source: the static cyclic part, then claims from the stolen tail
+  // (one call site of the body keeps a single inlined copy of the cuts).
+  const int G = gridDim.x;
+  const int tail = F - Fs;
+  int range = 0, fe = 0;   // stealing state: sub-ranges visited, end of the current claim
+  auto claim_next = [&]() -> int {
+    for (; tail > 0 && range < kClaimRanges; ++range) {
+      const int k = (int)((blockIdx.x + range) % kClaimRanges);
+      const int r0 = Fs + (int)((int64_t)tail * k / kClaimRanges);
+      const int r1 = Fs + (int)((int64_t)tail * (k + 1) / kClaimRanges);
+      int32_t* ctr = claims + kClaimStride * k;
       int base = r1;
       if (lane == 0) {
         const int seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (seen < r1 - r0) base = r0 + atomicAdd(ctr, claim);
       }
       base = __shfl(base, 0, 64);
-      if (base >= r1) break;
-      const int fe = base + claim < r1 ? base + claim : r1;
-      for (int f = base; f < fe; ++f) {
-        selected += cut_frame(f, X, Y, Z, lo, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
-        if constexpr (kFuse) {
-          while (cur.used - done >= kWave) fit(kWave);
-        }
+      if (base < r1) {
+        fe = base + claim < r1 ? base + claim : r1;
+        return base;
       }
     }
-  }
+    return -1;
+  };
+  auto next = [&](int g) -> int {
+    if (g < Fs) {
+      if (g < Fs - G) return g + G;
+      return claim_next();
+    }
+    if (g + 1 < fe) return g + 1;
+    return claim_next();
+  };
+  frame_pipeline((int)blockIdx.x < Fs ? (int)blockIdx.x : claim_next(), next, body, lo, X, Y, Z, n_hits);
   if constexpr (kFuse) {
     if (cur.used > done) fit(cur.used - done);
   }
@@ -1094,7 +1174,7 @@ __global__ void k_zero(int32_t* __restrict__ p, int n) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters, chunks, trips, res, sfit, sall, redo, vt, vok, ccnt, vbase, vpos, cand, total;
+  size_t counters, claims, chunks, trips, res, sfit, sall, redo, vt, vok, ccnt, vbase, vpos, cand, total;
 };
 
 // Entries of each slice table: at most ceil(count / 64) slices per chunk.
@@ -1104,6 +1184,7 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   Layout L;
   size_t o = 0;
   L.counters = o; o += align256(kCounters * sizeof(int32_t));
+  L.claims = o; o += align256((size_t)kClaimRanges * kClaimStride * sizeof(int32_t));
   L.chunks = o; o += align256((size_t)(tc / kMinChunk + 1) * 4 * sizeof(int32_t));
   L.trips = o; o += align256((size_t)tc * 2 * sizeof(int32_t));
   L.res = o; o += align256((size_t)tc * 4 * sizeof(int32_t));
@@ -1156,7 +1237,7 @@ int device_cus() {
 
 // Pointers into a caller workspace.
 struct WsView {
-  int32_t *counters, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok;
+  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok;
   Slices S;
   VTrack* vt;
   int redo_cap;
@@ -1166,6 +1247,7 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   char* ws = static_cast<char*>(workspace);
   WsView W;
   W.counters = reinterpret_cast<int32_t*>(ws + L.counters);
+  W.claims = reinterpret_cast<int32_t*>(ws + L.claims);
   W.chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
   W.trips = reinterpret_cast<int32_t*>(ws + L.trips);
   W.res = reinterpret_cast<int32_t*>(ws + L.res);
@@ -1413,7 +1495,7 @@ struct mu3e_plan {
   int32_t* counts;
   float* vertex;
   TripList T;
-  int F, P, cus, tcap, kcap;
+  int F, Fs, P, cus, tcap, kcap;
 };
 
 // The batched sequence: clear counters, persistent cuts (and fits), the fits
@@ -1424,15 +1506,17 @@ static void plan_launch(const mu3e_plan& pl, hipStream_t s, hipEvent_t* ev) {
   const TrackOut O = track_out(pl.W, pl.counts);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, pl.W.counters, kCounters);
   if (pl.F == 0) return;
+  if (pl.Fs < pl.F)
+    hipLaunchKernelGGL(k_zero, dim3(kClaimRanges), dim3(256), 0, s, pl.W.claims, kClaimRanges * kClaimStride);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (pl.tuning.fuse_fits)
-    hipLaunchKernelGGL(k_batched<true>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, h.n_hits,
-                       pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
-                       pl.tuning.frames_per_claim);
-  else
-    hipLaunchKernelGGL(k_batched<false>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F,
+    hipLaunchKernelGGL(k_batched<true>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, pl.Fs,
                        h.n_hits, pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
-                       pl.tuning.frames_per_claim);
+                       pl.W.claims, pl.tuning.frames_per_claim);
+  else
+    hipLaunchKernelGGL(k_batched<false>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, pl.Fs,
+                       h.n_hits, pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
+                       pl.W.claims, pl.tuning.frames_per_claim);
   if (ev) (void)hipEventRecord(ev[1], s);
   // fits left by the persistent kernel (all of them without fusion)
   launch_tracks(h, pl.C, pl.cus, pl.W, pl.T, pl.flags, pl.counts, s, ev ? ev[2] : nullptr);
@@ -1461,6 +1545,8 @@ mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const m
   t.waves_per_cu = tuning && tuning->waves_per_cu > 0 ? tuning->waves_per_cu : 16;
   t.frames_per_claim = tuning && tuning->frames_per_claim > 0 ? tuning->frames_per_claim : 4;
   t.fuse_fits = tuning ? (tuning->fuse_fits != 0) : 0;
+  t.steal_percent = tuning ? tuning->steal_percent : 0;
+  if (t.steal_percent < 0 || t.steal_percent > 100) return MU3E_ERR_INVALID_ARG;
   // persistent: never more waves than can be resident at once
   int resident = 0;
   const hipError_t oe = t.fuse_fits
@@ -1480,6 +1566,7 @@ mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const m
   pl->T = trip_list(W, triplet_capacity, P);
   pl->dbg.chunks = W.chunks; pl->dbg.max_chunks = triplet_capacity / kMinChunk + 1; pl->dbg.chunk_size = pl->T.chunk;
   pl->F = F; pl->P = P; pl->cus = cus; pl->tcap = triplet_capacity; pl->kcap = track_capacity;
+  pl->Fs = F - (int)((int64_t)F * t.steal_percent / 100);
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return MU3E_ERR_HIP; }
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;

@@ -63,7 +63,7 @@ class Debug(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("frames_per_claim", ctypes.c_int32),
-                ("fuse_fits", ctypes.c_int32)]
+                ("fuse_fits", ctypes.c_int32), ("steal_percent", ctypes.c_int32)]
 
 
 def make_params(p: dict) -> Params:
@@ -280,12 +280,12 @@ class BatchedSelector(Selector):
 
     def __init__(self, hits: DeviceHits, params: dict, triplet_capacity: int | None = None,
                  track_capacity: int | None = None, device="cuda", waves_per_cu: int = 0,
-                 frames_per_claim: int = 0, fuse_fits: int = 0):
+                 frames_per_claim: int = 0, fuse_fits: int = 0, steal_percent: int = 0):
         super().__init__(hits.n_frames, params, triplet_capacity, track_capacity, device)
         L = load()
         self.hits = hits
         self._hs = hits.struct()
-        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim), int(fuse_fits))
+        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim), int(fuse_fits), int(steal_percent))
         plan = ctypes.c_void_p()
         _check(L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(self._hs), ctypes.byref(self.params),
                                   _ptr(self.flags), _ptr(self.counts), _ptr(self.vertex), _ptr(self.ws),
@@ -294,7 +294,7 @@ class BatchedSelector(Selector):
         self.plan = plan
         eff = Tuning()
         _check(L.mu3e_plan_info(self.plan, ctypes.byref(self.dbg), ctypes.byref(eff)), "mu3e_plan_info")
-        self.effective = (eff.waves_per_cu, eff.frames_per_claim, eff.fuse_fits)
+        self.effective = (eff.waves_per_cu, eff.frames_per_claim, eff.fuse_fits, eff.steal_percent)
 
     def run(self, hits: DeviceHits = None, stream=None, events=None):
         """events: optional ctypes array of 4 hipEvent_t; then the plan's

@@ -83,3 +83,17 @@ def test_host_validation(L):
     assert L.mu3e_vertex(ctypes.byref(h), None, ctypes.byref(p), 1, 1, 1, 1, 1 << 20, None) == -1
     tr = lib.Tracks(80, 96, 4, 1000)
     assert L.mu3e_vertex(ctypes.byref(h), ctypes.byref(tr), ctypes.byref(p), 1, 1, 1, 1, 8, None) == -3
+    # triplet capacity beyond 2^30
+    assert L.mu3e_select_workspace_size(10, (1 << 30) + 1, 10) == 0
+    assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, (1 << 30) + 1, 10, None,
+                                None) == -1
+    # plan: null out pointer, invalid steal share (checked before any device call)
+    t = lib.Tuning(8, 4, 0, 101)
+    assert L.mu3e_plan_create(None, ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10,
+                              ctypes.byref(t)) == -1
+    plan = ctypes.c_void_p()
+    assert L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10,
+                              ctypes.byref(t)) == -1
+    assert plan.value is None
+    # timed plan run without a plan or events
+    assert L.mu3e_plan_run_timed(None, None, None) == -1

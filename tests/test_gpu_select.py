@@ -246,17 +246,17 @@ def test_full_nominal_sampled(lib):
     assert np.all(counts >= 0)
 
 
-@pytest.mark.parametrize("cfg,n,fuse", [(2, 3000, 0), (3, 5000, 1), (1, 1000, 0), (2, 2000, 1)])
-def test_batched_equals_plain_and_oracle(lib, cfg, n, fuse):
+@pytest.mark.parametrize("cfg,n,fuse,steal", [(2, 3000, 0, 25), (3, 5000, 1, 50), (1, 1000, 0, 0), (2, 2000, 1, 100)])
+def test_batched_equals_plain_and_oracle(lib, cfg, n, fuse, steal):
     """The batched persistent form gives exactly the plain form's outputs
     and matches the oracle."""
     import torch
     fs = synth.generate(cfg, n_frames=n)
     p = default_params()
     dh = lib.to_device(fs)
-    print(f"case: batched cfg{cfg}[:{n}] fused={fuse}", flush=True)
+    print(f"case: batched cfg{cfg}[:{n}] fused={fuse} steal={steal}%", flush=True)
     a = lib.select_frames(dh, p)
-    b = lib.BatchedSelector(dh, p, waves_per_cu=8, frames_per_claim=4, fuse_fits=fuse)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=8, frames_per_claim=4, fuse_fits=fuse, steal_percent=steal)
     b.run()
     torch.cuda.synchronize()
     fa, ca, va = a.result()
@@ -273,16 +273,16 @@ def test_batched_equals_plain_and_oracle(lib, cfg, n, fuse):
     assert_parity(bad, stats, f"batched cfg{cfg}")
 
 
-@pytest.mark.parametrize("w,c,fuse", [(1, 1, 1), (2, 32, 0), (20, 3, 1), (32, 8, 0)])
-def test_batched_shapes_and_repeat(lib, w, c, fuse):
+@pytest.mark.parametrize("w,c,fuse,steal", [(1, 1, 1, 100), (2, 32, 0, 50), (20, 3, 1, 0), (32, 8, 0, 12)])
+def test_batched_shapes_and_repeat(lib, w, c, fuse, steal):
     """Any shape gives the same result, also on a second run of the plan."""
     import torch
     fs = synth.generate(3, n_frames=4000)
     p = default_params()
     dh = lib.to_device(fs)
     ref = lib.select_frames(dh, p)
-    print(f"case: batched shape {w} waves/CU, {c} frames/claim, fused={fuse}", flush=True)
-    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=fuse)
+    print(f"case: batched shape {w} waves/CU, {c} frames/claim, fused={fuse}, steal={steal}%", flush=True)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=fuse, steal_percent=steal)
     for rep in range(2):
         b.run()
         torch.cuda.synchronize()
