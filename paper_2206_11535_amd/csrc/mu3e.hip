@@ -1,25 +1,34 @@
 // HIP kernels (gfx950) and C ABI of the online event selection.
 //
-// Plain form of the selection, three stages per batch of frames:
+// Plain form of the selection, per batch of frames:
 //   k_cuts     one wave64 per frame, frames dealt cyclically to a static grid
 //              (Section V-B, Alg. 1 and Alg. 2): the frame's layer-0..2 hits
 //              are staged in LDS; per layer-1 hit a 128-bit mask of layer-0
 //              partners passing the Phi01 window is built; (h1, h2) pairs
 //              passing Phi12 are streamed through an LDS queue and each full
 //              wave of pairs joins against its Phi01 partners (Delta lambda,
-//              then r_tc); survivors are compacted with ballot/popcount into an
-//              LDS buffer and appended to a global triplet list.
-//   k_tracks   one thread per selected triplet over the flat list (Alg. 3):
+//              then r_tc); survivors are compacted with ballot/popcount into
+//              the wave's chunks of a global triplet list.
+//   k_scount / k_splace  tables of the 64-entry slices of the list's chunks.
+//   k_tracks   one wave per slice, one lane per selected triplet (Alg. 3):
 //              fit, layer-3 extension, second fit, weighted curvature,
-//              chi2 < 32; tracks are pushed onto a per-frame list.
-//   k_vcand    per frame: track cap, frames able to form an e+e+e- triple
-//   k_vprep    per track of such frames: float64 refit
+//              chi2 < 32; the result is stored at the triplet's own index.
+//   k_vcount / k_vplace  per frame: track cap; frames able to form an
+//              e+e+e- triple get a slice of the candidate track table.
+//   k_vprep    per accepted track of such frames: float64 refit.
 //   k_vframes  one wave per candidate frame: energy test over the triples,
 //              combination cap, vertex estimate and signal tests (Alg. 4).
+// The batched form runs the cuts (and optionally the fits) in one
+// persistent kernel and captures the whole sequence in a HIP graph.
 //
 // Decisions taken on float32 values are certain with respect to the exact
 // value unless the value lies within a bound of its own rounding error around
 // the edge; then the candidate is re-evaluated in float64.
+//
+// No shared counter is updated per frame or per triplet: device-scope
+// atomics on one address serialise across the chip, so lists are handed out
+// in chunks, results are stored in place and reservations are made per wave
+// or by prefix sums.
 
 #include "mu3e.h"
 #include "mu3e_math.hpp"
@@ -118,6 +127,36 @@ __device__ inline int wave_max(int v) {
 }
 
 // ------------------------------------------------------------- cut tests
+// Each test decides in float32 when the value lies outside a bound of its own
+// rounding error around the window edges, and otherwise re-evaluates in
+// float64.  The float64 paths are separate non-inlined functions: inlined,
+// the compiler hoists their loop-invariant parts (divisions, square roots)
+// out of the join loop and runs them for every candidate.
+
+__device__ __attribute__((noinline, cold)) bool cos_refine(float x0, float y0, float x1, float y1, float lo,
+                                                            float hi, float Ra, float Rb) {
+  const double cd = ((double)x0 * x1 + (double)y0 * y1) / ((double)Ra * (double)Rb);
+  return cd >= (double)lo && cd <= (double)hi;
+}
+
+__device__ __attribute__((noinline, cold)) bool dl_refine(float z0, float z1, float z2, float R0, float R1, float R2,
+                                                           float lo, float hi) {
+  const double d = ((double)z2 - (double)z1) / ((double)R2 - (double)R1) -
+                   ((double)z1 - (double)z0) / ((double)R1 - (double)R0);
+  return d >= (double)lo && d <= (double)hi;
+}
+
+__device__ __attribute__((noinline, cold)) bool rtc_refine(float x0, float y0, float x1, float y1, float x2, float y2,
+                                                            float lo, float hi) {
+  const double dax = (double)x0 - x1, day = (double)y0 - y1, dbx = (double)x2 - x1, dby = (double)y2 - y1;
+  const double dex = (double)x2 - x0, dey = (double)y2 - y0;
+  const double cross = dax * dby - day * dbx;
+  if (cross == 0.0) return false;
+  const double r = sqrt(dax * dax + day * day) * sqrt(dbx * dbx + dby * dby) * sqrt(dex * dex + dey * dey) /
+                   (2.0 * fabs(cross));
+  return r >= (double)lo && r <= (double)hi;
+}
+
 // cos(Phi_ij) = (h_i . h_j) / (R_i R_j) in a closed window.
 __device__ inline bool cos_cut(float x0, float y0, float x1, float y1, float invRR, float lo, float hi,
                                float Ra, float Rb) {
@@ -126,8 +165,7 @@ __device__ inline bool cos_cut(float x0, float y0, float x1, float y1, float inv
   const float err = 8.0f * kU32 * (fabsf(a) + fabsf(b)) * invRR;
   if (c - err > lo && c + err < hi) return true;
   if (c + err < lo || c - err > hi) return false;
-  const double cd = ((double)x0 * x1 + (double)y0 * y1) / ((double)Ra * (double)Rb);
-  return cd >= (double)lo && cd <= (double)hi;
+  return cos_refine(x0, y0, x1, y1, lo, hi, Ra, Rb);
 }
 
 // Delta lambda = tan(lambda_12) - tan(lambda_01) in a closed window.
@@ -137,9 +175,7 @@ __device__ inline bool dl_cut(float z0, float z1, float z2, float t12, const Con
   const float err = 8.0f * kU32 * (fabsf(t01) + fabsf(t12) + fabsf(dl));
   if (dl - err > C.dl_lo && dl + err < C.dl_hi) return true;
   if (dl + err < C.dl_lo || dl - err > C.dl_hi) return false;
-  const double d = ((double)z2 - (double)z1) / ((double)C.R[2] - (double)C.R[1]) -
-                   ((double)z1 - (double)z0) / ((double)C.R[1] - (double)C.R[0]);
-  return d >= (double)C.dl_lo && d <= (double)C.dl_hi;
+  return dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
 }
 
 // |r_tc| in a closed window, tested as r_tc^2 = d01^2 d12^2 d20^2 / (4 cross^2)
@@ -158,13 +194,7 @@ __device__ inline bool rtc_cut(float x0, float y0, float x1, float y1, float x2,
   const float lo2 = C.rtc_lo2, hi2 = C.rtc_hi2;
   if (dlo > 0.0f && nlo >= lo2 * dhi * m && nhi * m <= hi2 * dlo) return true;
   if (nhi * m < lo2 * dlo || nlo > hi2 * dhi * m) return false;
-  const double dax = (double)x0 - x1, day = (double)y0 - y1, dbx = (double)x2 - x1, dby = (double)y2 - y1;
-  const double dex = (double)x2 - x0, dey = (double)y2 - y0;
-  const double cross = dax * dby - day * dbx;
-  if (cross == 0.0) return false;
-  const double r = sqrt(dax * dax + day * day) * sqrt(dbx * dbx + dby * dby) * sqrt(dex * dex + dey * dey) /
-                   (2.0 * fabs(cross));
-  return r >= (double)C.rtc_lo && r <= (double)C.rtc_hi;
+  return rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
 }
 
 // =================================================================== k_cuts
@@ -514,49 +544,75 @@ struct Slices {
   int32_t* all;
 };
 
-__device__ inline int block_exclusive_scan(int v, int* tmp, int& total) {
-  // 1024 threads: inclusive Hillis-Steele scan in LDS
+// Sums of a and b over a block of 256 threads (all threads get them).
+__device__ inline void block_sum2(int& a, int& b, int* tmp) {   // 256 threads
   const int i = threadIdx.x;
-  tmp[i] = v;
+  tmp[i] = a;
+  tmp[256 + i] = b;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int a = i >= o ? tmp[i - o] : 0;
-    __syncthreads();
-    tmp[i] += a;
+  for (int o = 128; o > 0; o >>= 1) {
+    if (i < o) { tmp[i] += tmp[i + o]; tmp[256 + i] += tmp[256 + i + o]; }
     __syncthreads();
   }
-  const int incl = tmp[i];
-  total = tmp[1023];
+  a = tmp[0];
+  b = tmp[256];
   __syncthreads();
-  return incl - v;
 }
 
-__global__ void __launch_bounds__(1024)
-k_slices(TripList T, Slices S, int32_t* __restrict__ counters) {
-  __shared__ int tmp[1024];
+// Slice counts of chunk c: fit slices of [fitted, count), all slices of
+// [0, count).
+__device__ inline void chunk_slices(const TripList& T, int c, int& nf, int& na) {
+  const int n = T.chunks[4 * c + 1];
+  const int from = T.chunks[4 * c + 2];
+  na = (n + kWave - 1) / kWave;
+  nf = from < n ? (n - from + kWave - 1) / kWave : 0;
+}
+
+// Two passes without atomics, 256 chunks per block: k_scount writes each
+// block's slice totals, k_splace offsets each block by the totals of the
+// blocks before it and writes the tables.
+__global__ void __launch_bounds__(256)
+k_scount(TripList T, int32_t* __restrict__ blk, const int32_t* __restrict__ counters) {
+  __shared__ int tmp[512];
   const int nch = chunks_granted(T, counters);
-  int base_f = 0, base_a = 0;
-  for (int c0 = 0; c0 < nch; c0 += 1024) {
-    const int c = c0 + (int)threadIdx.x;
-    int nf = 0, na = 0, from = 0;
-    if (c < nch) {
-      const int n = T.chunks[4 * c + 1];
-      from = T.chunks[4 * c + 2];
-      na = (n + kWave - 1) / kWave;
-      nf = from < n ? (n - from + kWave - 1) / kWave : 0;
-    }
-    int tf, ta;
-    const int of = block_exclusive_scan(nf, tmp, tf);
-    const int oa = block_exclusive_scan(na, tmp, ta);
-    for (int j = 0; j < nf; ++j) S.fit[base_f + of + j] = c * kWave + j;
-    for (int j = 0; j < na; ++j) S.all[base_a + oa + j] = c * kWave + j;
-    base_f += tf;
-    base_a += ta;
+  const int c = blockIdx.x * 256 + (int)threadIdx.x;
+  int nf = 0, na = 0;
+  if (c < nch) chunk_slices(T, c, nf, na);
+  block_sum2(nf, na, tmp);
+  if (threadIdx.x == 0) { blk[2 * blockIdx.x] = nf; blk[2 * blockIdx.x + 1] = na; }
+}
+
+__global__ void __launch_bounds__(256)
+k_splace(TripList T, Slices S, const int32_t* __restrict__ blk, int32_t* __restrict__ counters) {
+  __shared__ int tmp[512];
+  const int nch = chunks_granted(T, counters);
+  int bf = 0, ba = 0, tf = 0, ta = 0;
+  for (int j = threadIdx.x; j < (int)gridDim.x; j += 256) {
+    const int f = blk[2 * j], a = blk[2 * j + 1];
+    tf += f; ta += a;
+    if (j < (int)blockIdx.x) { bf += f; ba += a; }
   }
-  if (threadIdx.x == 0) {
-    counters[9] = base_f;
-    counters[10] = base_a;
+  block_sum2(bf, ba, tmp);
+  block_sum2(tf, ta, tmp);
+  if (blockIdx.x == 0 && threadIdx.x == 0) { counters[9] = tf; counters[10] = ta; }
+  const int c = blockIdx.x * 256 + (int)threadIdx.x;
+  int nf = 0, na = 0;
+  if (c < nch) chunk_slices(T, c, nf, na);
+  // block exclusive scan of (nf, na)
+  tmp[threadIdx.x] = nf;
+  tmp[256 + threadIdx.x] = na;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int i = threadIdx.x;
+    const int x = i >= o ? tmp[i - o] : 0, y = i >= o ? tmp[256 + i - o] : 0;
+    __syncthreads();
+    tmp[i] += x;
+    tmp[256 + i] += y;
+    __syncthreads();
   }
+  const int of = bf + tmp[threadIdx.x] - nf, oa = ba + tmp[256 + threadIdx.x] - na;
+  for (int j = 0; j < nf; ++j) S.fit[of + j] = c * kWave + j;
+  for (int j = 0; j < na; ++j) S.all[oa + j] = c * kWave + j;
 }
 
 // Float32 track reconstruction of the entries [fitted, count) of every
@@ -960,53 +1016,91 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
 // Frames able to form an e+e+e- triple (two e+ and one e- tracks, no
 // overflow so far) get a slice of the candidate track table; frames with
 // more than max_tracks tracks are flagged (Alg. 3: "marked for storage").
+// Two passes without atomics: k_vcount counts per block of frames,
+// k_vplace offsets each block by the counts of the blocks before it.  Block
+// b of kVBlocks-sized grids owns frames [b * per, (b + 1) * per).
+constexpr int kVBlocks = 512;
+
+__device__ inline bool vertex_candidate(int f, const Consts& C, const uint32_t* __restrict__ flags,
+                                        const int32_t* __restrict__ counts, const int32_t* __restrict__ ccnt,
+                                        int& nt) {
+  nt = 0;
+  if (flags[f] & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF | MU3E_TRACK_OVF)) return false;
+  nt = counts[3 * f + 1];
+  if (nt > C.max_trk) return false;
+  const int cc = ccnt[f];
+  return (cc & 0xffff) >= 2 && (cc >> 16) >= 1;
+}
+
+
 __global__ void __launch_bounds__(256)
-k_vcand(int F, Consts C, uint32_t* __restrict__ flags, const int32_t* __restrict__ counts,
-        const int32_t* __restrict__ ccnt, int32_t* __restrict__ vbase, int32_t* __restrict__ vpos,
-        int32_t* __restrict__ cand, int vcap, int32_t* __restrict__ counters) {
-  // one thread per frame; candidate slots and table slices are reserved with
-  // one atomic per wave (ballot rank and a wave prefix sum of track counts)
-  const int lane = threadIdx.x & 63;
-  const int stride = gridDim.x * blockDim.x;
-  for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < F; base += stride) {
-    const int f = base + lane;
+k_vcount(int F, int per, Consts C, uint32_t* __restrict__ flags, const int32_t* __restrict__ counts,
+         const int32_t* __restrict__ ccnt, int32_t* __restrict__ blk) {
+  __shared__ int tmp[512];
+  const int f0 = blockIdx.x * per, f1 = min(F, f0 + per);
+  int nc = 0, ntot = 0;
+  for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
+    const uint32_t fl = flags[f];
+    if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF)) && counts[3 * f + 1] > C.max_trk)
+      flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP;
+    int nt;
+    if (vertex_candidate(f, C, flags, counts, ccnt, nt)) { ++nc; ntot += nt; }
+  }
+  block_sum2(nc, ntot, tmp);
+  if (threadIdx.x == 0) { blk[2 * blockIdx.x] = nc; blk[2 * blockIdx.x + 1] = ntot; }
+}
+
+__global__ void __launch_bounds__(256)
+k_vplace(int F, int per, Consts C, const uint32_t* __restrict__ flags, const int32_t* __restrict__ counts,
+         const int32_t* __restrict__ ccnt, const int32_t* __restrict__ blk, int32_t* __restrict__ vbase,
+         int32_t* __restrict__ vpos, int32_t* __restrict__ cand, int vcap, int32_t* __restrict__ counters) {
+  __shared__ int tmp[1024];
+  const int B = gridDim.x;
+  // offsets of this block: the counts of the blocks before it (and totals)
+  int cb = 0, tb = 0, ca = 0, ta = 0;
+  for (int j = threadIdx.x; j < B; j += 256) {
+    const int c = blk[2 * j], t = blk[2 * j + 1];
+    ca += c; ta += t;
+    if (j < (int)blockIdx.x) { cb += c; tb += t; }
+  }
+  block_sum2(cb, tb, tmp);
+  block_sum2(ca, ta, tmp);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counters[3] = ca;
+    counters[4] = ta;
+    if (ta > vcap) atomicOr(&counters[2], ST_TRACK_FULL);
+  }
+  const int f0 = blockIdx.x * per, f1 = min(F, f0 + per);
+  for (int base = f0; base < f1; base += 256) {
+    const int f = base + (int)threadIdx.x;
     int nt = 0;
-    bool is_cand = false;
-    if (f < F) {
-      vbase[f] = -1;
-      const uint32_t fl = flags[f];
-      if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF))) {
-        nt = counts[3 * f + 1];
-        if (nt > C.max_trk) {
-          flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP;
-        } else {
-          const int cc = ccnt[f];
-          is_cand = (cc & 0xffff) >= 2 && (cc >> 16) >= 1;
-        }
+    const bool is_c = f < f1 && vertex_candidate(f, C, flags, counts, ccnt, nt);
+    // block exclusive scan of (is_c, nt) over the tile
+    tmp[threadIdx.x] = is_c ? 1 : 0;
+    tmp[256 + threadIdx.x] = is_c ? nt : 0;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const int i = threadIdx.x;
+      const int a = i >= o ? tmp[i - o] : 0, b = i >= o ? tmp[256 + i - o] : 0;
+      __syncthreads();
+      tmp[i] += a;
+      tmp[256 + i] += b;
+      __syncthreads();
+    }
+    const int ec = tmp[threadIdx.x] - (is_c ? 1 : 0), et = tmp[256 + threadIdx.x] - (is_c ? nt : 0);
+    const int tc = tmp[255], tt = tmp[511];
+    if (f < f1) {
+      if (is_c) {
+        vbase[f] = tb + et;
+        vpos[f] = 0;
+        cand[cb + ec] = f;
+      } else {
+        vbase[f] = -1;
       }
     }
-    const unsigned long long bm = __ballot(is_cand);
-    if (bm == 0ull) continue;   // wave-uniform
-    int incl = is_cand ? nt : 0;   // inclusive prefix sum of candidate track counts
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += v;
-    }
-    const int total = __shfl(incl, 63, 64);
-    int c0 = 0, t0 = 0;
-    if (lane == 0) {
-      c0 = atomicAdd(&counters[3], __popcll(bm));
-      t0 = atomicAdd(&counters[4], total);
-      if (t0 + total > vcap) atomicOr(&counters[2], ST_TRACK_FULL);
-    }
-    c0 = __shfl(c0, 0, 64);
-    t0 = __shfl(t0, 0, 64);
-    if (is_cand) {
-      vbase[f] = t0 + incl - nt;
-      vpos[f] = 0;
-      cand[c0 + __popcll(bm & lanemask_lt())] = f;
-    }
+    cb += tc;
+    tb += tt;
+    __syncthreads();
   }
 }
 
@@ -1031,7 +1125,7 @@ k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* _
     const int b = vbase[f];
     if (b < 0) continue;
     const int pos = atomicAdd(&vpos[f], 1);
-    if (b + pos >= vcap) continue;   // table full: reported by k_vcand
+    if (b + pos >= vcap) continue;   // table full: reported by k_vplace
     const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
     const int32_t h[4] = {lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
                           lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3] + res[4 * e + 1]};
@@ -1174,7 +1268,7 @@ __global__ void k_zero(int32_t* __restrict__ p, int n) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters, claims, chunks, trips, res, sfit, sall, redo, vt, vok, ccnt, vbase, vpos, cand, total;
+  size_t counters, claims, chunks, trips, res, sfit, sall, sblk, redo, vt, vok, ccnt, vbase, vpos, cand, vblk, total;
 };
 
 // Entries of each slice table: at most ceil(count / 64) slices per chunk.
@@ -1190,6 +1284,7 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.res = o; o += align256((size_t)tc * 4 * sizeof(int32_t));
   L.sfit = o; o += align256((size_t)slice_capacity(tc) * sizeof(int32_t));
   L.sall = o; o += align256((size_t)slice_capacity(tc) * sizeof(int32_t));
+  L.sblk = o; o += align256((size_t)2 * ((tc / kMinChunk + 1 + 255) / 256) * sizeof(int32_t));
   L.redo = o; o += align256((size_t)(kc / 8 + 1024) * sizeof(int32_t));
   L.vt = o; o += align256((size_t)kc * sizeof(VTrack));
   L.vok = o; o += align256((size_t)kc * sizeof(int32_t));
@@ -1197,6 +1292,7 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.vbase = o; o += align256((size_t)F * sizeof(int32_t));
   L.vpos = o; o += align256((size_t)F * sizeof(int32_t));
   L.cand = o; o += align256((size_t)F * sizeof(int32_t));
+  L.vblk = o; o += align256((size_t)2 * kVBlocks * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -1237,7 +1333,7 @@ int device_cus() {
 
 // Pointers into a caller workspace.
 struct WsView {
-  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok;
+  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok, *vblk, *sblk;
   Slices S;
   VTrack* vt;
   int redo_cap;
@@ -1253,6 +1349,7 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.res = reinterpret_cast<int32_t*>(ws + L.res);
   W.S.fit = reinterpret_cast<int32_t*>(ws + L.sfit);
   W.S.all = reinterpret_cast<int32_t*>(ws + L.sall);
+  W.sblk = reinterpret_cast<int32_t*>(ws + L.sblk);
   W.redo = reinterpret_cast<int32_t*>(ws + L.redo);
   W.vt = reinterpret_cast<VTrack*>(ws + L.vt);
   W.vok = reinterpret_cast<int32_t*>(ws + L.vok);
@@ -1260,6 +1357,7 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.vbase = reinterpret_cast<int32_t*>(ws + L.vbase);
   W.vpos = reinterpret_cast<int32_t*>(ws + L.vpos);
   W.cand = reinterpret_cast<int32_t*>(ws + L.cand);
+  W.vblk = reinterpret_cast<int32_t*>(ws + L.vblk);
   W.redo_cap = track_capacity / 8 + 1024;
   return W;
 }
@@ -1295,7 +1393,9 @@ TripList trip_list(const WsView& W, int capacity, int waves) {
 void launch_tracks(const mu3e_hits_t& h, const Consts& C, int cus, const WsView& W, const TripList& T,
                    const uint32_t* flags, int32_t* counts, hipStream_t stream, hipEvent_t after_fits) {
   const TrackOut O = track_out(W, counts);
-  hipLaunchKernelGGL(k_slices, dim3(1), dim3(1024), 0, stream, T, W.S, W.counters);
+  const int nbk = (int)(((int64_t)T.capacity / T.chunk + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_scount, dim3(nbk), dim3(256), 0, stream, T, W.sblk, W.counters);
+  hipLaunchKernelGGL(k_splace, dim3(nbk), dim3(256), 0, stream, T, W.S, W.sblk, W.counters);
   hipLaunchKernelGGL(k_tracks, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, flags, T,
                      W.S, O, W.counters);
   if (after_fits) (void)hipEventRecord(after_fits, stream);
@@ -1307,9 +1407,13 @@ void launch_tracks(const mu3e_hits_t& h, const Consts& C, int cus, const WsView&
 // capacity of the candidate track table.
 void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const WsView& W, const TripList& T,
                    uint32_t* flags, int32_t* counts, float* vtx, int vcap, hipStream_t stream, hipEvent_t* ev) {
-  const int gf = (F + 255) / 256 < cus * 8 ? (F + 255) / 256 : cus * 8;
-  hipLaunchKernelGGL(k_vcand, dim3(gf), dim3(256), 0, stream, F, C, flags, counts, W.ccnt, W.vbase, W.vpos, W.cand,
-                     vcap, W.counters);
+  int nb = (F + 255) / 256;
+  if (nb > kVBlocks) nb = kVBlocks;
+  const int per = ((F + nb - 1) / nb + 255) / 256 * 256;
+  nb = (F + per - 1) / per;
+  hipLaunchKernelGGL(k_vcount, dim3(nb), dim3(256), 0, stream, F, per, C, flags, counts, W.ccnt, W.vblk);
+  hipLaunchKernelGGL(k_vplace, dim3(nb), dim3(256), 0, stream, F, per, C, flags, counts, W.ccnt, W.vblk, W.vbase,
+                     W.vpos, W.cand, vcap, W.counters);
   hipLaunchKernelGGL(k_vprep, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets, C, T,
                      W.S, W.res, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok);
   if (ev) (void)hipEventRecord(ev[3], stream);
@@ -1360,8 +1464,9 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
   if (F > 0 && (!frame_flags || !frame_counts || !frame_vertex)) return MU3E_ERR_INVALID_ARG;
   const WsView W = ws_view(workspace, L, track_capacity);
   const int cus = device_cus();
-  // waves of the cuts kernel: 16 per CU, at least enough for 2048 frames each
-  int g1 = cus * 16;
+  // waves of the cuts kernel: 20 per CU (all resident), at least enough for
+  // 2048 frames each
+  int g1 = cus * 20;
   if (g1 < (F + 2047) / 2048) g1 = (F + 2047) / 2048;
   if (g1 > F) g1 = F > 0 ? F : 1;
   const TripList T = trip_list(W, triplet_capacity, g1);
