@@ -53,9 +53,13 @@ constexpr int kClaimStride = 1024;           // int32 apart (4 KiB)
 
 // counters: [0] triplets selected, [2] status bits, [3] candidate frames of
 // the vertex stage, [4] their track-table size, [5] entries queued for the
-// float64 re-evaluation, [7] triplet-list entries handed out in chunks (also past the capacity:
-// each grant adds one chunk), [9] and [10] lengths of the slice tables
+// float64 re-evaluation, [7] triplet-list entries handed out in chunks
+// (also past the capacity: each grant adds one chunk), [9] and [10] lengths
+// of the slice tables
 enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
+
+// Value of lane k (uniform k) in every lane: one v_readlane, no LDS crossbar.
+__device__ inline int lane_value(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
 
 // ----------------------------------------------------------- triplet list
 // Selected triplets are appended to chunks of one list: a wave takes a chunk
@@ -106,8 +110,8 @@ __device__ inline void cursor_open(Cursor& c, const TripList& T, int32_t* __rest
       atomicOr(&counters[2], ST_TRIP_FULL);
     }
   }
-  start = __shfl(start, 0, 64);
-  id = __shfl(id, 0, 64);
+  start = lane_value(start, 0);
+  id = lane_value(id, 0);
   c.start = start < 0 ? 0 : start;
   c.cap = start < 0 ? 0 : T.chunk;
   c.used = 0;
@@ -118,12 +122,6 @@ __device__ inline void cursor_open(Cursor& c, const TripList& T, int32_t* __rest
 __device__ inline uint64_t lanemask_lt() {
   const unsigned lane = threadIdx.x & 63u;
   return lane ? (~0ull >> (64u - lane)) : 0ull;
-}
-
-__device__ inline int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
 }
 
 // ------------------------------------------------------------- cut tests
@@ -222,7 +220,7 @@ __device__ inline int load_offsets(const int32_t* __restrict__ lo, int f, bool v
 // inside [b0, b3) and [0, n_hits) are read (malformed offsets read nothing).
 __device__ inline void load_hits(FrameRegs& R, const float* __restrict__ X, const float* __restrict__ Y,
                                  const float* __restrict__ Z, int n_hits, bool valid) {
-  const int b0 = __shfl(R.lo, 0, 64), b3 = __shfl(R.lo, 3, 64);
+  const int b0 = lane_value(R.lo, 0), b3 = lane_value(R.lo, 3);
   const int i = b0 + (int)threadIdx.x;
   R.x = R.y = R.z = 0.f;
   if (valid && b0 >= 0 && i < b3 && i < n_hits) {
@@ -247,8 +245,8 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
                          uint32_t* __restrict__ flags, int32_t* __restrict__ counts, float* __restrict__ vtx,
                          int32_t* __restrict__ ccnt, int32_t* __restrict__ counters) {
   const int lane = threadIdx.x;
-  const int b0 = __shfl(R.lo, 0, 64), b1 = __shfl(R.lo, 1, 64), b2 = __shfl(R.lo, 2, 64);
-  const int b3 = __shfl(R.lo, 3, 64), b4 = __shfl(R.lo, 4, 64);
+  const int b0 = lane_value(R.lo, 0), b1 = lane_value(R.lo, 1), b2 = lane_value(R.lo, 2);
+  const int b3 = lane_value(R.lo, 3), b4 = lane_value(R.lo, 4);
   const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2, n3 = b4 - b3;
   if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
   if (lane == 0) { ccnt[f] = 0; counts[3 * f + 1] = 0; counts[3 * f + 2] = 0; }
@@ -297,8 +295,7 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const float t12 = (z2 - z1) * C.inv12;
       unsigned long long w0 = have ? L.sm01[2 * i1] : 0ull, w1 = have ? L.sm01[2 * i1 + 1] : 0ull;
       const int nb = __popcll(w0) + __popcll(w1);
-      const int nmax = wave_max(nb);
-      for (int it = 0; it < nmax; ++it) {
+      for (int it = 0; __ballot(it < nb) != 0ull; ++it) {   // until every lane is out of partners
         const bool act = it < nb;
         int i0 = 0;
         if (act) {
@@ -498,7 +495,7 @@ __device__ inline void emit_result(bool active, int r, int e, int f, int i3, flo
   int qbase = 0;
   if (und != 0ull) {
     if (threadIdx.x == 0) qbase = atomicAdd(&counters[5], __popcll(und));
-    qbase = __shfl(qbase, 0, 64);
+    qbase = lane_value(qbase, 0);
   }
   if (!active) return;
   if (r < 0) {
@@ -697,7 +694,7 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
         const int seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (seen < r1 - r0) base = r0 + atomicAdd(ctr, claim);
       }
-      base = __shfl(base, 0, 64);
+      base = lane_value(base, 0);
       if (base < r1) {
         fe = base + claim < r1 ? base + claim : r1;
         return base;
