@@ -52,7 +52,8 @@ constexpr int kClaimRanges = 8;              // claim counters of the batched fo
 constexpr int kClaimStride = 1024;           // int32 apart (4 KiB)
 
 // counters: [0] triplets selected, [2] status bits, [3] candidate frames of
-// the vertex stage, [4] their track-table size, [5] entries queued for the
+// the vertex stage, [4] their track-table size, [11] those with more tracks
+// than slots, [5] entries queued for the
 // float64 re-evaluation, [7] triplet-list entries handed out in chunks
 // (also past the capacity: each grant adds one chunk), [9] and [10] lengths
 // of the slice tables
@@ -155,30 +156,37 @@ __device__ __attribute__((noinline, cold)) bool rtc_refine(float x0, float y0, f
   return r >= (double)lo && r <= (double)hi;
 }
 
+// Classification of a float32 test value: sure pass, sure fail, or
+// ambiguous (within its rounding-error bound of an edge: decided by the
+// float64 refinement).  Computed without branches; callers refine the
+// ambiguous lanes behind one wave-uniform ballot.
+struct Verdict {
+  bool pass, amb;
+};
+
+__device__ inline Verdict window(float v, float err, float lo, float hi) {
+  Verdict r;
+  r.pass = v - err > lo && v + err < hi;
+  r.amb = !r.pass && !(v + err < lo || v - err > hi);
+  return r;
+}
+
 // cos(Phi_ij) = (h_i . h_j) / (R_i R_j) in a closed window.
-__device__ inline bool cos_cut(float x0, float y0, float x1, float y1, float invRR, float lo, float hi,
-                               float Ra, float Rb) {
+__device__ inline Verdict cos_test(float x0, float y0, float x1, float y1, float invRR, float lo, float hi) {
   const float a = x0 * x1, b = y0 * y1;
-  const float c = (a + b) * invRR;
-  const float err = 8.0f * kU32 * (fabsf(a) + fabsf(b)) * invRR;
-  if (c - err > lo && c + err < hi) return true;
-  if (c + err < lo || c - err > hi) return false;
-  return cos_refine(x0, y0, x1, y1, lo, hi, Ra, Rb);
+  return window((a + b) * invRR, 8.0f * kU32 * (fabsf(a) + fabsf(b)) * invRR, lo, hi);
 }
 
 // Delta lambda = tan(lambda_12) - tan(lambda_01) in a closed window.
-__device__ inline bool dl_cut(float z0, float z1, float z2, float t12, const Consts& C) {
+__device__ inline Verdict dl_test(float z0, float z1, float t12, const Consts& C) {
   const float t01 = (z1 - z0) * C.inv01;
   const float dl = t12 - t01;
-  const float err = 8.0f * kU32 * (fabsf(t01) + fabsf(t12) + fabsf(dl));
-  if (dl - err > C.dl_lo && dl + err < C.dl_hi) return true;
-  if (dl + err < C.dl_lo || dl - err > C.dl_hi) return false;
-  return dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
+  return window(dl, 8.0f * kU32 * (fabsf(t01) + fabsf(t12) + fabsf(dl)), C.dl_lo, C.dl_hi);
 }
 
 // |r_tc| in a closed window, tested as r_tc^2 = d01^2 d12^2 d20^2 / (4 cross^2)
 // with bounds on the rounding of the cross product and the chords.
-__device__ inline bool rtc_cut(float x0, float y0, float x1, float y1, float x2, float y2, const Consts& C) {
+__device__ inline Verdict rtc_test(float x0, float y0, float x1, float y1, float x2, float y2, const Consts& C) {
   const float ax = x0 - x1, ay = y0 - y1, bx = x2 - x1, by = y2 - y1, ex = x2 - x0, ey = y2 - y0;
   const float pa = ax * by, pb = ay * bx;
   const float cr = fabsf(pa - pb);
@@ -190,16 +198,31 @@ __device__ inline bool rtc_cut(float x0, float y0, float x1, float y1, float x2,
   const float nlo = num * (1.0f - en), nhi = num * (1.0f + en);
   const float m = 1.0f + 16.0f * kU32;
   const float lo2 = C.rtc_lo2, hi2 = C.rtc_hi2;
-  if (dlo > 0.0f && nlo >= lo2 * dhi * m && nhi * m <= hi2 * dlo) return true;
-  if (nhi * m < lo2 * dlo || nlo > hi2 * dhi * m) return false;
-  return rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
+  Verdict r;
+  r.pass = dlo > 0.0f && nlo >= lo2 * dhi * m && nhi * m <= hi2 * dlo;
+  r.amb = !r.pass && !(nhi * m < lo2 * dlo || nlo > hi2 * dhi * m);
+  return r;
+}
+
+// The Phi window of a pair, refined where ambiguous (all lanes call).
+__device__ inline bool cos_cut_wave(bool act, float x0, float y0, float x1, float y1, float invRR, float lo,
+                                    float hi, float Ra, float Rb) {
+  const Verdict v = cos_test(x0, y0, x1, y1, invRR, lo, hi);
+  bool pass = act && v.pass;
+  if (__ballot(act && v.amb) != 0ull) {
+    if (act && v.amb) pass = cos_refine(x0, y0, x1, y1, lo, hi, Ra, Rb);
+  }
+  return pass;
 }
 
 // =================================================================== k_cuts
+constexpr int kJoinQueue = 128;   // (h0, h1, h2) combinations tested per round of a join
+
 struct CutLds {
   float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
   unsigned long long sm01[2 * kMaxLayerHits];
   uint32_t spend[2 * kWave];
+  uint32_t sjoin[kJoinQueue];   // packed i1 | i2 << 8 | i0 << 16
 };
 
 // ------------------------------------------------------------ frame loads
@@ -233,8 +256,8 @@ __device__ inline void load_hits(FrameRegs& R, const float* __restrict__ X, cons
 // Selection Cuts of frame f by one wave (Alg. 2): the frame's layer-0..2
 // hits are staged in LDS; a 128-bit mask of layer-0 partners passing Phi01
 // per layer-1 hit; (h1, h2) pairs passing Phi12 are streamed through an LDS
-// queue and each full wave of pairs is joined against its Phi01 partners
-// (Delta lambda, then r_tc).  Survivors are ballot-compacted into the
+// queue and each full wave of pairs is joined against its Phi01 partners,
+// the combinations tested a full wave at a time (Delta lambda, then r_tc).  Survivors are ballot-compacted into the
 // wave's chunks of the triplet list (cur; done = the wave's fitted prefix of
 // its current chunk, recorded when the chunk is closed); returns the number
 // committed (0 when the frame overflows max_triplets) and writes the frame's
@@ -277,53 +300,84 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     // ---- Phi01 over all (i0, i1) pairs
     const int n01 = n0 * n1;
     const float r0 = 1.0f / (float)n0;
-    for (int p = lane; p < n01; p += kWave) {
-      const int i1 = (int)(((float)p + 0.5f) * r0);   // exact for p < 2^14
-      const int i0 = p - i1 * n0;
-      if (cos_cut(L.sx[i0], L.sy[i0], L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], C.invRR01, C.c01_lo,
-                  C.c01_hi, C.R[0], C.R[1]))
+    for (int base = 0; base < n01; base += kWave) {
+      const int p = base + lane;
+      const bool act = p < n01;
+      const int i1 = act ? (int)(((float)p + 0.5f) * r0) : 0;   // exact for p < 2^14
+      const int i0 = act ? p - i1 * n0 : 0;
+      if (cos_cut_wave(act, L.sx[i0], L.sy[i0], L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], C.invRR01,
+                       C.c01_lo, C.c01_hi, C.R[0], C.R[1]))
         atomicOr(&L.sm01[2 * i1 + (i0 >> 6)], 1ull << (i0 & 63));
     }
     __syncthreads();
+    // Join of the k pending (h1, h2) pairs with their Phi01 partners: the
+    // combinations are expanded into an LDS queue (positions from a wave
+    // prefix sum of the partner counts, built from bit-plane ballots) and
+    // tested kWave at a time, so that every lane has a combination.
     auto join = [&](int k) {
       const bool have = lane < k;
       const uint32_t e = have ? L.spend[lane] : 0u;
-      const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
-      const float x1 = L.sx[kMaxLayerHits + i1], y1 = L.sy[kMaxLayerHits + i1], z1 = L.sz[kMaxLayerHits + i1];
-      const float x2 = L.sx[2 * kMaxLayerHits + i2], y2 = L.sy[2 * kMaxLayerHits + i2];
-      const float z2 = L.sz[2 * kMaxLayerHits + i2];
-      const float t12 = (z2 - z1) * C.inv12;
+      const uint32_t i1 = e & 0xff;
       unsigned long long w0 = have ? L.sm01[2 * i1] : 0ull, w1 = have ? L.sm01[2 * i1 + 1] : 0ull;
-      const int nb = __popcll(w0) + __popcll(w1);
-      for (int it = 0; __ballot(it < nb) != 0ull; ++it) {   // until every lane is out of partners
-        const bool act = it < nb;
-        int i0 = 0;
-        if (act) {
+      const int nb = __popcll(w0) + __popcll(w1);   // <= kMaxLayerHits
+      int pos = 0, tot = 0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const unsigned long long m = __ballot((nb >> b) & 1);
+        pos += __popcll(m & lanemask_lt()) << b;
+        tot += __popcll(m) << b;
+      }
+      for (int lo = 0; lo < tot; lo += kJoinQueue) {
+        const int hi = tot < lo + kJoinQueue ? tot : lo + kJoinQueue;
+        // this lane's combinations with positions in [lo, hi) (earlier ones
+        // were written in earlier rounds)
+        while (pos < hi && (w0 | w1) != 0ull) {
+          int i0;
           if (w0) { i0 = __ffsll((long long)w0) - 1; w0 &= w0 - 1; }
           else { i0 = 64 + __ffsll((long long)w1) - 1; w1 &= w1 - 1; }
+          L.sjoin[pos - lo] = e | ((uint32_t)i0 << 16);
+          ++pos;
         }
-        bool pass = false;
-        if (act) pass = dl_cut(L.sz[i0], z1, z2, t12, C) && rtc_cut(L.sx[i0], L.sy[i0], x1, y1, x2, y2, C);
-        const unsigned long long bm = __ballot(pass);
-        const int c = __popcll(bm);
-        if (c > 0) {
-          if (cur.used + c > cur.cap && !cur.full) {
-            cursor_close(cur, done, T);
-            cursor_open(cur, T, counters);
-            done = 0;
+        __syncthreads();
+        const int m = hi - lo;
+        for (int q0 = 0; q0 < m; q0 += kWave) {
+          const bool act = q0 + lane < m;
+          const uint32_t c3 = act ? L.sjoin[q0 + lane] : 0u;
+          const int j1 = c3 & 0xff, j2 = (c3 >> 8) & 0xff, j0 = (c3 >> 16) & 0xff;
+          const float x0 = L.sx[j0], y0 = L.sy[j0], z0 = L.sz[j0];
+          const float x1 = L.sx[kMaxLayerHits + j1], y1 = L.sy[kMaxLayerHits + j1];
+          const float z1 = L.sz[kMaxLayerHits + j1];
+          const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
+          const float z2 = L.sz[2 * kMaxLayerHits + j2];
+          const Verdict vd = dl_test(z0, z1, (z2 - z1) * C.inv12, C);
+          const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
+          bool dpass = vd.pass, rpass = vr.pass;
+          if (__ballot(act && (vd.amb || vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
+            if (act && vd.amb) dpass = dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
+            if (act && vr.amb && dpass) rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
           }
-          if (cur.cap > 0) {
-            if (pass) {
-              const int slot = cur.start + cur.used + __popcll(bm & lanemask_lt());
-              T.trips[2 * slot] = f;
-              T.trips[2 * slot + 1] = (int32_t)((uint32_t)i0 | ((uint32_t)i1 << 8) | ((uint32_t)i2 << 16));
+          const bool pass = act && dpass && rpass;
+          const unsigned long long bm = __ballot(pass);
+          const int c = __popcll(bm);
+          if (c > 0) {
+            if (cur.used + c > cur.cap && !cur.full) {
+              cursor_close(cur, done, T);
+              cursor_open(cur, T, counters);
+              done = 0;
             }
-            cur.used += c;
+            if (cur.cap > 0) {
+              if (pass) {
+                const int slot = cur.start + cur.used + __popcll(bm & lanemask_lt());
+                T.trips[2 * slot] = f;
+                T.trips[2 * slot + 1] = (int32_t)((uint32_t)j0 | ((uint32_t)j1 << 8) | ((uint32_t)j2 << 16));
+              }
+              cur.used += c;
+            }
           }
+          total += c;
         }
-        total += c;
+        __syncthreads();
       }
-      __syncthreads();
     };
     // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
     int npend = 0;
@@ -331,12 +385,13 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     const float r2 = 1.0f / (float)n2;
     for (int base = 0; base < n12; base += kWave) {
       const int p = base + lane;
-      const int i1 = (int)(((float)p + 0.5f) * r2);
-      const int i2 = p - i1 * n2;
-      bool pass = false;
-      if (p < n12 && (L.sm01[2 * i1] | L.sm01[2 * i1 + 1]) != 0ull)
-        pass = cos_cut(L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], L.sx[2 * kMaxLayerHits + i2],
-                       L.sy[2 * kMaxLayerHits + i2], C.invRR12, C.c12_lo, C.c12_hi, C.R[1], C.R[2]);
+      const bool inr = p < n12;
+      const int i1 = inr ? (int)(((float)p + 0.5f) * r2) : 0;
+      const int i2 = inr ? p - i1 * n2 : 0;
+      const bool act = inr && (L.sm01[2 * i1] | L.sm01[2 * i1 + 1]) != 0ull;
+      const bool pass = cos_cut_wave(act, L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1],
+                                     L.sx[2 * kMaxLayerHits + i2], L.sy[2 * kMaxLayerHits + i2], C.invRR12,
+                                     C.c12_lo, C.c12_hi, C.R[1], C.R[2]);
       const unsigned long long bm = __ballot(pass);
       if (pass) L.spend[npend + __popcll(bm & lanemask_lt())] = (uint32_t)i1 | ((uint32_t)i2 << 8);
       npend += __popcll(bm);
@@ -469,20 +524,27 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
 // queued for the float64 re-evaluation, which rewrites the result.
 enum { TR_REJECT = 0, TR_ACCEPT = 1, TR_REDO = 2 };
 
+// Accepted tracks per frame also note their entry index in the frame's row of
+// tslot (the first kTrackSlots of them), so that the vertex stage finds the
+// tracks of its candidate frames without scanning the list.
+constexpr int kTrackSlots = 16;
+
 struct TrackOut {
   int32_t* res;      // [triplet capacity][4]
   int32_t* redo;     // [redo_cap] entry indices
   int redo_cap;
   int32_t* counts;   // per-frame counts [3F]; tracks at 3f + 1
   int32_t* ccnt;     // per-frame charge tally: +1 per e+, +65536 per e-
+  int32_t* tslot;    // [F][kTrackSlots] entry indices of accepted tracks
 };
 
 __device__ inline void store_result(int32_t* __restrict__ res, int e, int code, int i3, float kb, float c2) {
   *reinterpret_cast<int4*>(res + 4 * e) = make_int4(code, i3, __float_as_int(kb), __float_as_int(c2));
 }
 
-__device__ inline void tally_track(const TrackOut& O, int f, float kb) {
-  atomicAdd(&O.counts[3 * f + 1], 1);
+__device__ inline void tally_track(const TrackOut& O, int f, int e, float kb) {
+  const int rank = atomicAdd(&O.counts[3 * f + 1], 1);
+  if (rank < kTrackSlots) O.tslot[f * kTrackSlots + rank] = e;
   atomicAdd(&O.ccnt[f], kb > 0.f ? 1 : 65536);
 }
 
@@ -505,7 +567,7 @@ __device__ inline void emit_result(bool active, int r, int e, int f, int i3, flo
     store_result(O.res, e, TR_REDO, 0, 0.f, 0.f);
   } else {
     store_result(O.res, e, r == 1 ? TR_ACCEPT : TR_REJECT, i3, kb, c2);
-    if (r == 1) tally_track(O, f, kb);
+    if (r == 1) tally_track(O, f, e, kb);
   }
 }
 
@@ -730,7 +792,7 @@ k_tracks_redo(const float* __restrict__ X, const float* __restrict__ Y, const fl
     double kd = 0, cd = 0;
     const int r = fit_entry<double>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kd, cd);
     store_result(O.res, e, r == 1 ? TR_ACCEPT : TR_REJECT, i3, (float)kd, (float)cd);
-    if (r == 1) tally_track(O, f, (float)kd);
+    if (r == 1) tally_track(O, f, e, (float)kd);
   }
 }
 
@@ -1035,16 +1097,21 @@ k_vcount(int F, int per, Consts C, uint32_t* __restrict__ flags, const int32_t* 
          const int32_t* __restrict__ ccnt, int32_t* __restrict__ blk) {
   __shared__ int tmp[512];
   const int f0 = blockIdx.x * per, f1 = min(F, f0 + per);
-  int nc = 0, ntot = 0;
+  int nc = 0, ntot = 0, nbig = 0, unused = 0;
   for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
     const uint32_t fl = flags[f];
     if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF)) && counts[3 * f + 1] > C.max_trk)
       flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP;
     int nt;
-    if (vertex_candidate(f, C, flags, counts, ccnt, nt)) { ++nc; ntot += nt; }
+    if (vertex_candidate(f, C, flags, counts, ccnt, nt)) { ++nc; ntot += nt; nbig += nt > kTrackSlots; }
   }
   block_sum2(nc, ntot, tmp);
-  if (threadIdx.x == 0) { blk[2 * blockIdx.x] = nc; blk[2 * blockIdx.x + 1] = ntot; }
+  block_sum2(nbig, unused, tmp);
+  if (threadIdx.x == 0) {
+    blk[3 * blockIdx.x] = nc;
+    blk[3 * blockIdx.x + 1] = ntot;
+    blk[3 * blockIdx.x + 2] = nbig;   // candidate frames with more tracks than slots
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -1054,17 +1121,19 @@ k_vplace(int F, int per, Consts C, const uint32_t* __restrict__ flags, const int
   __shared__ int tmp[1024];
   const int B = gridDim.x;
   // offsets of this block: the counts of the blocks before it (and totals)
-  int cb = 0, tb = 0, ca = 0, ta = 0;
+  int cb = 0, tb = 0, ca = 0, ta = 0, big = 0, unused = 0;
   for (int j = threadIdx.x; j < B; j += 256) {
-    const int c = blk[2 * j], t = blk[2 * j + 1];
-    ca += c; ta += t;
+    const int c = blk[3 * j], t = blk[3 * j + 1];
+    ca += c; ta += t; big += blk[3 * j + 2];
     if (j < (int)blockIdx.x) { cb += c; tb += t; }
   }
   block_sum2(cb, tb, tmp);
   block_sum2(ca, ta, tmp);
+  block_sum2(big, unused, tmp);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     counters[3] = ca;
     counters[4] = ta;
+    counters[11] = big;
     if (ta > vcap) atomicOr(&counters[2], ST_TRACK_FULL);
   }
   const int f0 = blockIdx.x * per, f1 = min(F, f0 + per);
@@ -1101,14 +1170,16 @@ k_vplace(int F, int per, Consts C, const uint32_t* __restrict__ flags, const int
   }
 }
 
-// Float64 vertex-stage quantities of the accepted tracks of candidate
-// frames, placed in the frames' slices of the candidate table (vt, vok); one
-// wave per 64-entry slice of the triplet list.
+// Float64 vertex-stage quantities of the accepted tracks of candidate frames
+// with more tracks than slots, placed in the frames' slices of the candidate
+// table (vt, vok); one wave per 64-entry slice of the triplet list.  Returns
+// at once when there is no such frame.
 __global__ void __launch_bounds__(64)
 k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
         const int32_t* __restrict__ lo, Consts C, TripList T, Slices S, const int32_t* __restrict__ res,
-        const int32_t* __restrict__ counters, const int32_t* __restrict__ vbase, int32_t* __restrict__ vpos, int vcap,
-        VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
+        const int32_t* __restrict__ counts, const int32_t* __restrict__ counters, const int32_t* __restrict__ vbase,
+        int32_t* __restrict__ vpos, int vcap, VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
+  if (counters[11] == 0) return;   // every candidate frame's tracks are in its slot row
   const int ns = counters[10];
   for (int v = blockIdx.x; v < ns; v += gridDim.x) {
     const int pkd = S.all[v];
@@ -1120,7 +1191,7 @@ k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* _
     if (res[4 * e] != TR_ACCEPT) continue;
     const int f = T.trips[2 * e];
     const int b = vbase[f];
-    if (b < 0) continue;
+    if (b < 0 || counts[3 * f + 1] <= kTrackSlots) continue;
     const int pos = atomicAdd(&vpos[f], 1);
     if (b + pos >= vcap) continue;   // table full: reported by k_vplace
     const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
@@ -1135,17 +1206,40 @@ struct RangeId {
   __device__ int operator()(int j) const { return base + j; }
 };
 
+// One wave per candidate frame.  A frame with at most kTrackSlots tracks
+// refits them here (lanes over its slot row) into LDS; a larger one uses the
+// table slice filled by k_vprep.
 __global__ void __launch_bounds__(64)
-k_vframes_list(Consts C, const int32_t* __restrict__ counters, const int32_t* __restrict__ cand,
-               const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos, int vcap,
-               const VTrack* __restrict__ vt, const int32_t* __restrict__ vok, uint32_t* __restrict__ flags,
-               int32_t* __restrict__ counts, float* __restrict__ vtx) {
+k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
+               const int32_t* __restrict__ lo, Consts C, TripList T, const int32_t* __restrict__ res,
+               const int32_t* __restrict__ tslot, const int32_t* __restrict__ counters,
+               const int32_t* __restrict__ cand, const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos,
+               int vcap, const VTrack* __restrict__ vt, const int32_t* __restrict__ vok,
+               uint32_t* __restrict__ flags, int32_t* __restrict__ counts, float* __restrict__ vtx) {
+  __shared__ VTrack svt[kTrackSlots];
+  __shared__ int32_t svok[kTrackSlots];
+  const int lane = threadIdx.x;
   const int nc = counters[3];
   for (int c = blockIdx.x; c < nc; c += gridDim.x) {
     const int f = cand[c];
-    const int b = vbase[f], n = vpos[f];
-    if (b < 0 || b + n > vcap) continue;   // table full: reported in the status word
-    vertex_wave(f, n, RangeId{b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
+    const int nt = counts[3 * f + 1];
+    if (nt <= kTrackSlots) {
+      if (lane < nt) {
+        const int e = tslot[f * kTrackSlots + lane];
+        const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
+        const int32_t h[4] = {lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
+                              lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3] + res[4 * e + 1]};
+        VTrack v;
+        svok[lane] = vtrack_make(X, Y, Z, n_hits, h, C, v) ? 1 : 0;
+        svt[lane] = v;
+      }
+      __syncthreads();
+      vertex_wave(f, nt, RangeId{0}, svt, svok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
+    } else {
+      const int b = vbase[f], n = vpos[f];
+      if (b < 0 || b + n > vcap) continue;   // table full: reported in the status word
+      vertex_wave(f, n, RangeId{b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
+    }
   }
 }
 
@@ -1265,7 +1359,8 @@ __global__ void k_zero(int32_t* __restrict__ p, int n) {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t counters, claims, chunks, trips, res, sfit, sall, sblk, redo, vt, vok, ccnt, vbase, vpos, cand, vblk, total;
+  size_t counters, claims, chunks, trips, res, sfit, sall, sblk, redo, vt, vok, ccnt, vbase, vpos, cand, vblk, tslot,
+      total;
 };
 
 // Entries of each slice table: at most ceil(count / 64) slices per chunk.
@@ -1289,7 +1384,8 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.vbase = o; o += align256((size_t)F * sizeof(int32_t));
   L.vpos = o; o += align256((size_t)F * sizeof(int32_t));
   L.cand = o; o += align256((size_t)F * sizeof(int32_t));
-  L.vblk = o; o += align256((size_t)2 * kVBlocks * sizeof(int32_t));
+  L.vblk = o; o += align256((size_t)3 * kVBlocks * sizeof(int32_t));
+  L.tslot = o; o += align256((size_t)F * kTrackSlots * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -1330,7 +1426,7 @@ int device_cus() {
 
 // Pointers into a caller workspace.
 struct WsView {
-  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok, *vblk, *sblk;
+  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok, *vblk, *sblk, *tslot;
   Slices S;
   VTrack* vt;
   int redo_cap;
@@ -1355,6 +1451,7 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.vpos = reinterpret_cast<int32_t*>(ws + L.vpos);
   W.cand = reinterpret_cast<int32_t*>(ws + L.cand);
   W.vblk = reinterpret_cast<int32_t*>(ws + L.vblk);
+  W.tslot = reinterpret_cast<int32_t*>(ws + L.tslot);
   W.redo_cap = track_capacity / 8 + 1024;
   return W;
 }
@@ -1366,6 +1463,7 @@ TrackOut track_out(const WsView& W, int32_t* counts) {
   O.redo_cap = W.redo_cap;
   O.counts = counts;
   O.ccnt = W.ccnt;
+  O.tslot = W.tslot;
   return O;
 }
 
@@ -1412,10 +1510,13 @@ void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const 
   hipLaunchKernelGGL(k_vplace, dim3(nb), dim3(256), 0, stream, F, per, C, flags, counts, W.ccnt, W.vblk, W.vbase,
                      W.vpos, W.cand, vcap, W.counters);
   hipLaunchKernelGGL(k_vprep, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets, C, T,
-                     W.S, W.res, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok);
+                     W.S, W.res, counts, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok);
   if (ev) (void)hipEventRecord(ev[3], stream);
-  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, C, W.counters, W.cand, W.vbase, W.vpos,
-                     vcap, W.vt, W.vok, flags, counts, vtx);
+  // one wave per SIMD is resident (float64-heavy, many registers): no more
+  // blocks than that, so that every candidate frame starts at once
+  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 4), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets,
+                     C, T, W.res, W.tslot, W.counters, W.cand, W.vbase, W.vpos, vcap, W.vt, W.vok, flags, counts,
+                     vtx);
   if (ev) (void)hipEventRecord(ev[4], stream);
 }
 
