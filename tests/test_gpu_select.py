@@ -119,6 +119,47 @@ def test_signal_only_frames(lib):
     assert (flags & 16).sum() > 300
 
 
+def test_busy_signal_frames(lib):
+    """Signal decays on top of a high Michel rate: vertex-candidate frames
+    with more tracks than the per-frame slot row (the vertex stage then
+    gathers them from the whole triplet list)."""
+    cfg = dataclasses.replace(synth.CONFIGS[1], lam=22.0, noise_per_layer=2, signal_frac=1.0)
+    fs = synth.generate(cfg, n_frames=500, salt=13)
+    orc, flags, counts = check(lib, fs, default_params(), "busy signal frames", triplet_capacity=400 * 500)
+    many = (counts[:, 1] > 16) & ((flags & (2 | 4 | 32)) == 0)
+    assert many.sum() > 50
+    assert ((flags & 16) != 0)[many].sum() > 10
+
+
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_batched_small_chunks(lib, fuse):
+    """A small triplet capacity makes the chunks 64 entries long, so frames
+    span chunks, fused fits leave entries of closed chunks to k_tracks, and
+    an overflowing frame leaves entries behind in closed chunks."""
+    import torch
+    fs = synth.generate(2, n_frames=3000)
+    p = default_params(max_triplets=30)
+    dh = lib.to_device(fs)
+    print(f"case: batched small chunks fused={fuse}", flush=True)
+    a = lib.select_frames(dh, p, triplet_capacity=400000)
+    b = lib.BatchedSelector(dh, p, triplet_capacity=120000, waves_per_cu=4, frames_per_claim=2, fuse_fits=fuse,
+                            steal_percent=50)
+    b.run()
+    torch.cuda.synchronize()
+    assert b.dbg.chunk_size == 64
+    assert a.counters()[2] == 0
+    fa, ca, va = a.result()
+    fb, cb, vb = b.result()
+    assert np.array_equal(fa, fb) and np.array_equal(ca, cb)
+    assert np.array_equal(np.nan_to_num(va), np.nan_to_num(vb))
+    assert (fb & 2).sum() > 20   # frames over max_triplets
+    tb, kb, kfb, c = b.lists(fs.layer_offsets)
+    assert c[2] == 0
+    orc = oracle.run(fs, p)
+    bad, stats = compare(orc, fb, cb, vb, tb, kb, kfb)
+    assert_parity(bad, stats, f"batched small chunks fused={fuse}")
+
+
 def test_fit_triplets(lib):
     import torch
     fs = synth.generate(2, n_frames=3000)
