@@ -40,10 +40,14 @@ FLOPS_PER_L3_HIT = 8
 # 3 squared chords, their product, 4 cross^2, two scaled bounds) = 24.
 FLOPS_PAIR01, FLOPS_PAIR12, FLOPS_JOIN, FLOPS_RTC = 4, 6, 3, 24
 
-# HBM traffic of the roofline kernel on this workload from rocprofv3
-# FETCH_SIZE / WRITE_SIZE, keyed by "<hash of the kernel sources>|<kernel>"
-# of the build it was measured on (null once the source changes).
-TRAFFIC = {}
+# HBM bytes per launch of the roofline kernel on this workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy probe, keyed by
+# "<hash of the kernel sources>|<kernel>" of the build it was measured on
+# (null once the source changes).
+TRAFFIC = {
+    # profiles/nominal_hbm_traffic.md: 145.40 MB read + 77.68 MB written per launch
+    "f77eff57cadf5346|k_batched": 223080333,
+}
 
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X float32 vector (published)
 
