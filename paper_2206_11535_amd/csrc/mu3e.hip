@@ -866,79 +866,123 @@ __device__ inline double cone_dist(double r, double z, const Consts& C) {
   return best;
 }
 
-// Vertex estimate of one e+ e+ e- triple: returns true if a combination of
-// intersections passes all three signal tests; the minimum-chi2 passing
-// combination is returned in v[4].
-__device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C, double* v) {
+// Vertex estimate of one e+ e+ e- triple, in two parts so that a wave can
+// spread the combinations over its lanes.  VPoints: the intersections of the
+// three track circles pairwise (pairs (0,1), (0,2), (1,2)) that lie near the
+// target, and at each the mean of the two tracks' position variances.
+struct VPoints {
+  double qx[3][2], qy[3][2], s2[3][2];
+  int nq[3];
+};
+
+__device__ inline bool vertex_points(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C,
+                                     VPoints& P) {
   const VTrack* tk[3] = {T0, T1, T2};
   const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-  double qx[3][2], qy[3][2];
-  int nq[3];
   const double lim = (double)C.r_target + (double)C.target_tol;
   for (int k = 0; k < 3; ++k) {
     const VTrack& A = *tk[pa[k]];
     const VTrack& B = *tk[pb[k]];
     const double dx = B.cx - A.cx, dy = B.cy - A.cy;
     const double d = sqrt(dx * dx + dy * dy);
+    P.nq[k] = 0;
     if (d == 0.0 || d > A.rt + B.rt || d < fabs(A.rt - B.rt)) return false;
     const double a = (A.rt * A.rt - B.rt * B.rt + d * d) / (2.0 * d);
     const double h = sqrt(fmax(A.rt * A.rt - a * a, 0.0));
     const double ux = dx / d, uy = dy / d;
-    nq[k] = 0;
-    for (int s = -1; s <= 1; s += 2) {
-      const double x = A.cx + a * ux - s * h * uy, y = A.cy + a * uy + s * h * ux;
-      if (sqrt(x * x + y * y) <= lim) { qx[k][nq[k]] = x; qy[k][nq[k]] = y; ++nq[k]; }
+    // the two intersections (s = -1, +1), kept in that order if near the target
+    const double x0 = A.cx + a * ux + h * uy, y0 = A.cy + a * uy - h * ux;
+    const double x1 = A.cx + a * ux - h * uy, y1 = A.cy + a * uy + h * ux;
+    const bool in0 = sqrt(x0 * x0 + y0 * y0) <= lim, in1 = sqrt(x1 * x1 + y1 * y1) <= lim;
+    if (!in0 && !in1) return false;
+    const double fx = in0 ? x0 : x1, fy = in0 ? y0 : y1;
+    P.qx[k][0] = fx;
+    P.qy[k][0] = fy;
+    P.s2[k][0] = 0.5 * (sigma2_at(A, fx, fy, C) + sigma2_at(B, fx, fy, C));
+    P.nq[k] = 1;
+    if (in0 && in1) {
+      P.qx[k][1] = x1;
+      P.qy[k][1] = y1;
+      P.s2[k][1] = 0.5 * (sigma2_at(A, x1, y1, C) + sigma2_at(B, x1, y1, C));
+      P.nq[k] = 2;
     }
-    if (nq[k] == 0) return false;
   }
+  return true;
+}
+
+// Bit c of the mask: combination c (intersection c & 1 of pair 0, (c >> 1) & 1
+// of pair 1, (c >> 2) & 1 of pair 2) exists.
+__device__ inline int vertex_combos(const VPoints& P) {
+  int m = 0;
+  for (int c = 0; c < 8; ++c)
+    if ((c & 1) < P.nq[0] && ((c >> 1) & 1) < P.nq[1] && ((c >> 2) & 1) < P.nq[2]) m |= 1 << c;
+  return m;
+}
+
+// Combination c: weighted mean of its three intersections, points of closest
+// approach of the tracks, z back-projection, chi2 and the three signal tests;
+// v[4] = (x, y, z, chi2) when all pass.
+__device__ inline bool vertex_combo(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C,
+                                    const VPoints& P, int c, double* v) {
+  const VTrack* tk[3] = {T0, T1, T2};
+  double w = 0, mx = 0, my = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const bool second = (c >> k) & 1;   // selects without a dynamic index (no scratch)
+    const double x = second ? P.qx[k][1] : P.qx[k][0], y = second ? P.qy[k][1] : P.qy[k][0];
+    const double s2 = second ? P.s2[k][1] : P.s2[k][0];
+    w += 1.0 / s2; mx += x / s2; my += y / s2;
+  }
+  mx /= w; my /= w;
+  double px[3], py[3], pz[3], s2k[3];
+  for (int k = 0; k < 3; ++k) {
+    const VTrack& t = *tk[k];
+    const double ex = mx - t.cx, ey = my - t.cy;
+    const double en = sqrt(ex * ex + ey * ey);
+    if (en == 0.0) return false;
+    px[k] = t.cx + t.rt * ex / en;
+    py[k] = t.cy + t.rt * ey / en;
+    const double dphi = back_turn(t, px[k], py[k]);
+    pz[k] = t.hz - dphi * t.rbar * t.cth;
+    const double s = t.rt * dphi;
+    s2k[k] = t.sms0 * t.sms0 * s * s + (double)C.sig_pix * (double)C.sig_pix;
+  }
+  double wz = 0, mz = 0;
+  for (int k = 0; k < 3; ++k) { wz += 1.0 / s2k[k]; mz += pz[k] / s2k[k]; }
+  mz /= wz;
+  double chi2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double ex = px[k] - mx, ey = py[k] - my, ez = pz[k] - mz;
+    chi2 += (ex * ex + ey * ey + ez * ez) / s2k[k];
+  }
+  const double dt = cone_dist(sqrt(mx * mx + my * my), mz, C);
+  double sx = 0, sy = 0, sz = 0;
+  for (int k = 0; k < 3; ++k) {
+    const VTrack& t = *tk[k];
+    const double ux = (px[k] - t.cx) / t.rt, uy = (py[k] - t.cy) / t.rt;
+    const double pt = kCLight * (double)C.b * t.rt;
+    // travel direction: clockwise (positive) -> (uy, -ux)
+    sx += pt * t.q * uy;
+    sy -= pt * t.q * ux;
+    sz += t.p * t.cth;
+  }
+  const double ps = sqrt(sx * sx + sy * sy + sz * sz);
+  if (!(chi2 <= (double)C.chi2_v && dt <= (double)C.d_target && ps <= (double)C.p_sum)) return false;
+  v[0] = mx; v[1] = my; v[2] = mz; v[3] = chi2;
+  return true;
+}
+
+// All combinations of one triple in order: the passing one with the lowest
+// chi2 (the first of equal ones) in v[4].
+__device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C, double* v) {
+  VPoints P;
+  if (!vertex_points(T0, T1, T2, C, P)) return false;
+  const int m = vertex_combos(P);
   bool found = false;
   for (int c = 0; c < 8; ++c) {
-    const int sel[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-    if (sel[0] >= nq[0] || sel[1] >= nq[1] || sel[2] >= nq[2]) continue;
-    double w = 0, mx = 0, my = 0;
-    for (int k = 0; k < 3; ++k) {
-      const double x = qx[k][sel[k]], y = qy[k][sel[k]];
-      const double s2 = 0.5 * (sigma2_at(*tk[pa[k]], x, y, C) + sigma2_at(*tk[pb[k]], x, y, C));
-      w += 1.0 / s2; mx += x / s2; my += y / s2;
-    }
-    mx /= w; my /= w;
-    double px[3], py[3], pz[3], s2k[3];
-    bool ok = true;
-    for (int k = 0; k < 3; ++k) {
-      const VTrack& t = *tk[k];
-      const double ex = mx - t.cx, ey = my - t.cy;
-      const double en = sqrt(ex * ex + ey * ey);
-      if (en == 0.0) { ok = false; break; }
-      px[k] = t.cx + t.rt * ex / en;
-      py[k] = t.cy + t.rt * ey / en;
-      const double dphi = back_turn(t, px[k], py[k]);
-      pz[k] = t.hz - dphi * t.rbar * t.cth;
-      const double s = t.rt * dphi;
-      s2k[k] = t.sms0 * t.sms0 * s * s + (double)C.sig_pix * (double)C.sig_pix;
-    }
-    if (!ok) continue;
-    double wz = 0, mz = 0;
-    for (int k = 0; k < 3; ++k) { wz += 1.0 / s2k[k]; mz += pz[k] / s2k[k]; }
-    mz /= wz;
-    double chi2 = 0;
-    for (int k = 0; k < 3; ++k) {
-      const double ex = px[k] - mx, ey = py[k] - my, ez = pz[k] - mz;
-      chi2 += (ex * ex + ey * ey + ez * ez) / s2k[k];
-    }
-    const double dt = cone_dist(sqrt(mx * mx + my * my), mz, C);
-    double sx = 0, sy = 0, sz = 0;
-    for (int k = 0; k < 3; ++k) {
-      const VTrack& t = *tk[k];
-      const double ux = (px[k] - t.cx) / t.rt, uy = (py[k] - t.cy) / t.rt;
-      const double pt = kCLight * (double)C.b * t.rt;
-      // travel direction: clockwise (positive) -> (uy, -ux)
-      sx += pt * t.q * uy;
-      sy -= pt * t.q * ux;
-      sz += t.p * t.cth;
-    }
-    const double ps = sqrt(sx * sx + sy * sy + sz * sz);
-    if (chi2 <= (double)C.chi2_v && dt <= (double)C.d_target && ps <= (double)C.p_sum) {
-      if (!found || chi2 < v[3]) { v[0] = mx; v[1] = my; v[2] = mz; v[3] = chi2; }
+    double u[4];
+    if ((m >> c & 1) && vertex_combo(T0, T1, T2, C, P, c, u) && (!found || u[3] < v[3])) {
+      for (int k = 0; k < 4; ++k) v[k] = u[k];
       found = true;
     }
   }
@@ -1040,32 +1084,70 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     __syncthreads();
     return;
   }
-  // ---- vertex of every energy-passing triple
+  // ---- vertex of every energy-passing triple.  Per round of kWave triples:
+  // each lane finds the intersection points of one triple (into LDS), then
+  // the existing (triple, combination) pairs are evaluated a full wave at a
+  // time.  The result is the passing combination with the lowest chi2, ties
+  // to the lowest (triple index, combination).
+  __shared__ VPoints sP[kWave];
+  __shared__ int sT[3 * kWave];
+  __shared__ int sq[8 * kWave];
   double best = 1e300;
-  int bestk = 0x7fffffff;
+  long long bestk = 0x7fffffffffffffffLL;
   double bv[3] = {0, 0, 0};
   if (cnt > 0) {
-    for (int k = lane; k < total; k += kWave) {
-      int ta, tb, te;
-      decode(k, ta, tb, te);
-      const double s = vt[ta].E + vt[tb].E + vt[te].E;
-      if (!(s >= elo && s <= ehi)) continue;
-      double v[4];
-      if (vertex_triple(&vt[ta], &vt[tb], &vt[te], C, v) && v[3] < best) {
-        best = v[3]; bestk = k; bv[0] = v[0]; bv[1] = v[1]; bv[2] = v[2];
+    for (int base = 0; base < total; base += kWave) {
+      const int k = base + lane;
+      int ta = 0, tb = 0, te = 0;
+      bool ep = false;
+      if (k < total) {
+        decode(k, ta, tb, te);
+        const double s = vt[ta].E + vt[tb].E + vt[te].E;
+        ep = s >= elo && s <= ehi;
       }
+      if (__ballot(ep) == 0ull) continue;   // wave-uniform
+      VPoints P;
+      int m = 0;
+      if (ep && vertex_points(&vt[ta], &vt[tb], &vt[te], C, P)) m = vertex_combos(P);
+      if (m) sP[lane] = P;
+      sT[3 * lane] = ta; sT[3 * lane + 1] = tb; sT[3 * lane + 2] = te;
+      const int nc = __popc((unsigned)m);   // <= 8
+      int pos = 0, tot = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const unsigned long long mb = __ballot((nc >> b) & 1);
+        pos += __popcll(mb & lanemask_lt()) << b;
+        tot += __popcll(mb) << b;
+      }
+      for (int c = 0; c < 8; ++c)
+        if (m >> c & 1) sq[pos++] = lane * 8 + c;
+      __syncthreads();
+      for (int q0 = 0; q0 < tot; q0 += kWave) {
+        if (q0 + lane < tot) {
+          const int e = sq[q0 + lane];
+          const int l = e >> 3, c = e & 7;
+          double u[4];
+          if (vertex_combo(&vt[sT[3 * l]], &vt[sT[3 * l + 1]], &vt[sT[3 * l + 2]], C, sP[l], c, u)) {
+            const long long key = (long long)(base + l) * 8 + c;
+            if (u[3] < best || (u[3] == best && key < bestk)) {
+              best = u[3]; bestk = key; bv[0] = u[0]; bv[1] = u[1]; bv[2] = u[2];
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
   }
-  // wave-wide minimum of (chi2, triple index)
+  // wave-wide minimum of (chi2, key)
   double wb = best;
-  int wk = bestk;
+  long long wk = bestk;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const double ob = __shfl_xor(wb, o, 64);
-    const int ok = __shfl_xor(wk, o, 64);
+    const long long ok = __shfl_xor(wk, o, 64);
     if (ob < wb || (ob == wb && ok < wk)) { wb = ob; wk = ok; }
   }
-  if (wk != 0x7fffffff && bestk == wk) {
+  if (wk != 0x7fffffffffffffffLL && bestk == wk) {
     *flags |= MU3E_VERTEX | MU3E_KEEP;
     vtx[0] = (float)bv[0]; vtx[1] = (float)bv[1]; vtx[2] = (float)bv[2]; vtx[3] = (float)best;
   }
