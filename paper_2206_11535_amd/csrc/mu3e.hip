@@ -495,12 +495,26 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
   if (!reach) return 0;
   T best = (T)1e30, second = (T)1e30;
   int ib = -1;
-  for (int g = b3; g < b4; ++g) {
-    const T dx = (T)X[g] - px, dy = (T)Y[g] - py, dz = (T)Z[g] - pz;
+  auto consider = [&](float x, float y, float z, int g) {
+    const T dx = (T)x - px, dy = (T)y - py, dz = (T)z - pz;
     const T d2 = dx * dx + dy * dy + dz * dz;
     if (d2 < best) { second = best; best = d2; ib = g; }
     else if (d2 < second) second = d2;
+  };
+  // layer-3 hits in order, four at a time with 16-byte loads (dword-aligned
+  // addresses; all four inside [b3, b4)), then the rest one by one
+  int g = b3;
+  for (; g + 4 <= b4; g += 4) {
+    float4 vx, vy, vz;
+    __builtin_memcpy(&vx, X + g, sizeof(float4));
+    __builtin_memcpy(&vy, Y + g, sizeof(float4));
+    __builtin_memcpy(&vz, Z + g, sizeof(float4));
+    consider(vx.x, vy.x, vz.x, g);
+    consider(vx.y, vy.y, vz.y, g + 1);
+    consider(vx.z, vy.z, vz.z, g + 2);
+    consider(vx.w, vy.w, vz.w, g + 3);
   }
+  for (; g < b4; ++g) consider(X[g], Y[g], Z[g], g);
   if (ib < 0) return 0;
   if (F32 && second < (T)1e29) {
     const T eps = (T)1e-3;   // bound on the float32 error of the predicted point [mm]
@@ -677,7 +691,7 @@ k_splace(TripList T, Slices S, const int32_t* __restrict__ blk, int32_t* __restr
 // Float32 track reconstruction of the entries [fitted, count) of every
 // chunk, one wave per 64-entry slice (dealt cyclically to the grid);
 // candidates the float32 arithmetic cannot decide go to the float64 list.
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
          const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags, TripList T, Slices S,
          TrackOut O, int32_t* __restrict__ counters) {
