@@ -230,21 +230,15 @@ def test_deterministic_outputs(lib):
     assert sorted(map(tuple, ka.tolist())) == sorted(map(tuple, kb.tolist()))
 
 
-def test_full_nominal_sampled(lib):
-    """The benchmark workload (100,000 nominal frames, benchmark launch
-    configuration) compared with the oracle on 2,000 sampled frames."""
-    import torch
-    fs = synth.generate(2)
-    p = default_params()
-    print(f"case: full cfg2 {fs.n_frames} frames", flush=True)
-    dh = lib.to_device(fs)
-    sel = lib.select_frames(dh, p)
-    torch.cuda.synchronize()
+def sampled_parity(fs, p, sel, what, n_pick=2000, seed=7):
+    """Compare a selector's outputs over a whole batch with the oracle run
+    frame by frame on n_pick sampled frames; check properties that hold
+    for every frame."""
     flags, counts, vtx = sel.result()
     trips, tracks, kf, c = sel.lists(fs.layer_offsets)
     assert c[2] == 0
-    rng = np.random.default_rng(7)
-    pick = np.sort(rng.choice(fs.n_frames, 2000, replace=False))
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(fs.n_frames, n_pick, replace=False))
     # oracle on the picked frames, one sub-batch per frame (hit indices rebased)
     sub_trips, sub_tracks, sub_kf = [], [], []
     orcs = []
@@ -265,26 +259,64 @@ def test_full_nominal_sampled(lib):
         np.concatenate([o.counts for o in orcs]), np.concatenate([o.namb for o in orcs]),
         np.concatenate([o.vertex for o in orcs]), sum(o.stats for o in orcs), 0.0)
 
-    def cat(name, idx_cols, rows_of):
+    def cat(name, idx_cols):
         out = []
         for i, o in enumerate(orcs):
             a = getattr(o, name).copy()
             a[:, 0] = i
             out.append(a)
         return np.concatenate(out) if out else np.zeros((0, idx_cols))
-    orc.trips = cat("trips", 6, None)
+    orc.trips = cat("trips", 6)
     orc.trip_rtc = np.concatenate([o.trip_rtc for o in orcs])
-    orc.tracks = cat("tracks", 8, None)
+    orc.tracks = cat("tracks", 8)
     orc.track_f = np.concatenate([o.track_f for o in orcs])
-    orc.triples = cat("triples", 12, None)
+    orc.triples = cat("triples", 12)
     bad, stats = compare(orc, flags, counts, vtx, np.concatenate(sub_trips), np.concatenate(sub_tracks),
                          np.concatenate(sub_kf), frames=pick)
-    print("full cfg2 sampled", stats, flush=True)
-    assert_parity(bad, stats, "full cfg2 sampled")
+    print(what, stats, flush=True)
+    assert_parity(bad, stats, what)
     # properties over all frames: counts non-negative, KEEP iff another bit
     keep = (flags & 1) != 0
     assert np.array_equal(keep, (flags & 62) != 0)
     assert np.all(counts >= 0)
+
+
+def test_full_nominal_sampled(lib):
+    """The benchmark workload (100,000 nominal frames) in both forms, each in
+    the launch configuration the benchmark times (the batched form with the
+    autotuned shape), compared with the oracle on 2,000 sampled frames."""
+    import torch
+    from paper_2206_11535_amd import autotune
+    fs = synth.generate(2)
+    p = default_params()
+    print(f"case: full cfg2 {fs.n_frames} frames", flush=True)
+    dh = lib.to_device(fs)
+    sel = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    sampled_parity(fs, p, sel, "full cfg2 sampled, plain")
+    (w, c, u, st), _, _ = autotune.tune(dh, p)
+    print(f"case: full cfg2 batched shape {(w, c, u, st)}", flush=True)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=u, steal_percent=st)
+    b.run()
+    torch.cuda.synchronize()
+    sampled_parity(fs, p, b, "full cfg2 sampled, batched", seed=8)
+
+
+def test_full_mixed_sampled(lib):
+    """The mixed-rate 1,000,000-frame batch in the batched form with the
+    autotuned shape, compared with the oracle on 2,000 sampled frames."""
+    import torch
+    from paper_2206_11535_amd import autotune
+    fs = synth.generate(3)
+    p = default_params()
+    print(f"case: full cfg3 {fs.n_frames} frames", flush=True)
+    dh = lib.to_device(fs)
+    (w, c, u, st), _, _ = autotune.tune(dh, p)
+    print(f"case: full cfg3 batched shape {(w, c, u, st)}", flush=True)
+    b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=u, steal_percent=st)
+    b.run()
+    torch.cuda.synchronize()
+    sampled_parity(fs, p, b, "full cfg3 sampled, batched", seed=9)
 
 
 @pytest.mark.parametrize("cfg,n,fuse,steal", [(2, 3000, 0, 25), (3, 5000, 1, 50), (1, 1000, 0, 0), (2, 2000, 1, 100)])
