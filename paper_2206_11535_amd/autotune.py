@@ -99,6 +99,9 @@ def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: i
                   flush=True)
         del sel
     best = min(table, key=lambda r: r[4])
+    # entries measured on other kernel sources are stale: drop them
+    tag = f"|src{source_tag()}|"
+    cache = {k: v for k, v in cache.items() if "|src" not in k or tag in k}
     cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "fuse_fits": best[2],
                   "steal_percent": best[3], "ms": best[4]}
     with open(CACHE, "w") as f:
