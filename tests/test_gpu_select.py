@@ -109,6 +109,38 @@ def test_empty_and_tiny_frames(lib):
     check(lib, fs, default_params(), "tiny frames")
 
 
+def test_batched_empty_and_tiny(lib):
+    """The batched form on a batch without frames, on one frame, and on the
+    tiny frames above (every shape), against the plain form."""
+    import torch
+    from helpers import Frames
+    frames = [[[], [], [], []],
+              [[(25.0, 0.0, 1.0)], [], [(73.0, 0.0, 2.0)], []],
+              [[(25.0, 0.0, 1.0)], [(31.0, 0.5, 1.2)], [(73.0, 2.0, 2.0)], []],
+              [[], [], [], [(85.0, 0.0, 0.0)]]]
+    p = default_params()
+    for sub in ([], frames[2:3], frames):
+        fs = Frames(sub) if sub else None
+        if fs is None:
+            empty = Frames(frames[:1])
+            empty.layer_offsets = np.zeros(1, np.int32)
+            empty.x = empty.y = empty.z = np.zeros(0, np.float32)
+            empty.sensor = empty.layer = np.zeros(0, np.uint16)
+            fs = empty
+        print(f"case: batched tiny, {fs.n_frames} frames", flush=True)
+        dh = lib.to_device(fs)
+        a = lib.select_frames(dh, p)
+        for fuse in (0, 1):
+            b = lib.BatchedSelector(dh, p, waves_per_cu=4, frames_per_claim=1, fuse_fits=fuse, steal_percent=50)
+            b.run()
+            torch.cuda.synchronize()
+            fa, ca, va = a.result()
+            fb, cb, vb = b.result()
+            assert np.array_equal(fa, fb) and np.array_equal(ca, cb)
+            assert np.array_equal(np.nan_to_num(va), np.nan_to_num(vb))
+            assert b.counters()[2] == 0
+
+
 def test_misaligned_frames(lib):
     check(lib, synth.generate(5, n_frames=2000), default_params(), "cfg5[:2000]")
 
