@@ -216,7 +216,7 @@ __device__ inline bool cos_cut_wave(bool act, float x0, float y0, float x1, floa
 }
 
 // =================================================================== k_cuts
-constexpr int kJoinQueue = 128;   // (h0, h1, h2) combinations tested per round of a join
+constexpr int kJoinQueue = 2 * 64;   // combinations passing Delta lambda awaiting r_tc (< 2 waves)
 
 struct CutLds {
   float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
@@ -256,8 +256,9 @@ __device__ inline void load_hits(FrameRegs& R, const float* __restrict__ X, cons
 // Selection Cuts of frame f by one wave (Alg. 2): the frame's layer-0..2
 // hits are staged in LDS; a 128-bit mask of layer-0 partners passing Phi01
 // per layer-1 hit; (h1, h2) pairs passing Phi12 are streamed through an LDS
-// queue and each full wave of pairs is joined against its Phi01 partners,
-// the combinations tested a full wave at a time (Delta lambda, then r_tc).  Survivors are ballot-compacted into the
+// queue and each full wave of pairs is joined against its Phi01 partners
+// (Delta lambda tested as they are expanded), the combinations passing it
+// queued and tested on r_tc a full wave at a time.  Survivors are ballot-compacted into the
 // wave's chunks of the triplet list (cur; done = the wave's fitted prefix of
 // its current chunk, recorded when the chunk is closed); returns the number
 // committed (0 when the frame overflows max_triplets) and writes the frame's
@@ -282,16 +283,21 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     if (lane == 0) { flags[f] = MU3E_HITS_OVF | MU3E_KEEP; counts[3 * f] = 0; }
     return 0;
   }
-  // ---- stage the layer-0..2 hits of the frame (coalesced), clear the masks
+  // ---- stage the layer-0..2 hits of the frame (coalesced), clear the masks.
+  // Hits 0..63 arrive in registers loaded during the previous frame; the
+  // rest are loaded in a loop of their own, so that the common case waits
+  // on no memory load here (a wait would also cover the next frame's loads,
+  // issued just before this frame).
   const int n012 = n0 + n1 + n2;
-  for (int i = lane; i < n012; i += kWave) {
+  auto stage = [&](int i, float x, float y, float z) {
     const int l = (i >= n0) + (i >= n0 + n1);
     const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
-    const bool pre = i < kWave;   // hits 0..63 arrive prefetched in registers
-    L.sx[l * kMaxLayerHits + k] = pre ? R.x : X[b0 + i];
-    L.sy[l * kMaxLayerHits + k] = pre ? R.y : Y[b0 + i];
-    L.sz[l * kMaxLayerHits + k] = pre ? R.z : Z[b0 + i];
-  }
+    L.sx[l * kMaxLayerHits + k] = x;
+    L.sy[l * kMaxLayerHits + k] = y;
+    L.sz[l * kMaxLayerHits + k] = z;
+  };
+  if (lane < n012) stage(lane, R.x, R.y, R.z);
+  for (int i = kWave + lane; i < n012; i += kWave) stage(i, X[b0 + i], Y[b0 + i], Z[b0 + i]);
   for (int i = lane; i < 2 * n1; i += kWave) L.sm01[i] = 0ull;
   __syncthreads();
   int total = 0;   // triplets passing all cuts (exact)
@@ -310,73 +316,77 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
         atomicOr(&L.sm01[2 * i1 + (i0 >> 6)], 1ull << (i0 & 63));
     }
     __syncthreads();
-    // Join of the k pending (h1, h2) pairs with their Phi01 partners: the
-    // combinations are expanded into an LDS queue (positions from a wave
-    // prefix sum of the partner counts, built from bit-plane ballots) and
-    // tested kWave at a time, so that every lane has a combination.
+    // r_tc test of the first m (<= kWave) queued combinations, one per lane;
+    // survivors are ballot-compacted into the wave's chunks of the list.
+    auto test = [&](int m) {
+      const bool act = lane < m;
+      const uint32_t c3 = act ? L.sjoin[lane] : 0u;
+      const int j1 = c3 & 0xff, j2 = (c3 >> 8) & 0xff, j0 = (c3 >> 16) & 0xff;
+      const float x0 = L.sx[j0], y0 = L.sy[j0];
+      const float x1 = L.sx[kMaxLayerHits + j1], y1 = L.sy[kMaxLayerHits + j1];
+      const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
+      const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
+      bool rpass = vr.pass;
+      if (__ballot(act && vr.amb) != 0ull) {   // rare: float64 where float32 cannot decide
+        if (act && vr.amb) rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
+      }
+      const bool pass = act && rpass;
+      const unsigned long long bm = __ballot(pass);
+      const int c = __popcll(bm);
+      if (c > 0) {
+        if (cur.used + c > cur.cap && !cur.full) {
+          cursor_close(cur, done, T);
+          cursor_open(cur, T, counters);
+          done = 0;
+        }
+        if (cur.cap > 0) {
+          if (pass) {
+            const int slot = cur.start + cur.used + __popcll(bm & lanemask_lt());
+            T.trips[2 * slot] = f;
+            T.trips[2 * slot + 1] = (int32_t)((uint32_t)j0 | ((uint32_t)j1 << 8) | ((uint32_t)j2 << 16));
+          }
+          cur.used += c;
+        }
+      }
+      total += c;
+    };
+    // Join of the k pending (h1, h2) pairs with their Phi01 partners: each
+    // lane visits its pair's partners one per round and tests Delta lambda
+    // (which needs only z); the passing combinations are ballot-compacted
+    // into an LDS queue, and each full wave of them is tested on r_tc, so
+    // that the costly test runs on full waves of the few survivors.
+    int nq = 0;   // queued combinations, < kWave between rounds
     auto join = [&](int k) {
       const bool have = lane < k;
       const uint32_t e = have ? L.spend[lane] : 0u;
-      const uint32_t i1 = e & 0xff;
+      const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
       unsigned long long w0 = have ? L.sm01[2 * i1] : 0ull, w1 = have ? L.sm01[2 * i1 + 1] : 0ull;
-      const int nb = __popcll(w0) + __popcll(w1);   // <= kMaxLayerHits
-      int pos = 0, tot = 0;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const unsigned long long m = __ballot((nb >> b) & 1);
-        pos += __popcll(m & lanemask_lt()) << b;
-        tot += __popcll(m) << b;
-      }
-      for (int lo = 0; lo < tot; lo += kJoinQueue) {
-        const int hi = tot < lo + kJoinQueue ? tot : lo + kJoinQueue;
-        // this lane's combinations with positions in [lo, hi) (earlier ones
-        // were written in earlier rounds)
-        while (pos < hi && (w0 | w1) != 0ull) {
-          int i0;
-          if (w0) { i0 = __ffsll((long long)w0) - 1; w0 &= w0 - 1; }
-          else { i0 = 64 + __ffsll((long long)w1) - 1; w1 &= w1 - 1; }
-          L.sjoin[pos - lo] = e | ((uint32_t)i0 << 16);
-          ++pos;
+      const float z1 = L.sz[kMaxLayerHits + i1], z2 = L.sz[2 * kMaxLayerHits + i2];
+      const float t12 = (z2 - z1) * C.inv12;
+      while (__ballot((w0 | w1) != 0ull) != 0ull) {
+        const bool has = (w0 | w1) != 0ull;
+        int i0 = 0;
+        if (w0) { i0 = __ffsll((long long)w0) - 1; w0 &= w0 - 1; }
+        else if (w1) { i0 = 64 + __ffsll((long long)w1) - 1; w1 &= w1 - 1; }
+        const float z0 = L.sz[i0];
+        const Verdict vd = dl_test(z0, z1, t12, C);
+        bool pass = has && vd.pass;
+        if (__ballot(has && vd.amb) != 0ull) {   // rare: float64 where float32 cannot decide
+          if (has && vd.amb) pass = dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
         }
-        __syncthreads();
-        const int m = hi - lo;
-        for (int q0 = 0; q0 < m; q0 += kWave) {
-          const bool act = q0 + lane < m;
-          const uint32_t c3 = act ? L.sjoin[q0 + lane] : 0u;
-          const int j1 = c3 & 0xff, j2 = (c3 >> 8) & 0xff, j0 = (c3 >> 16) & 0xff;
-          const float x0 = L.sx[j0], y0 = L.sy[j0], z0 = L.sz[j0];
-          const float x1 = L.sx[kMaxLayerHits + j1], y1 = L.sy[kMaxLayerHits + j1];
-          const float z1 = L.sz[kMaxLayerHits + j1];
-          const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
-          const float z2 = L.sz[2 * kMaxLayerHits + j2];
-          const Verdict vd = dl_test(z0, z1, (z2 - z1) * C.inv12, C);
-          const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
-          bool dpass = vd.pass, rpass = vr.pass;
-          if (__ballot(act && (vd.amb || vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
-            if (act && vd.amb) dpass = dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
-            if (act && vr.amb && dpass) rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
-          }
-          const bool pass = act && dpass && rpass;
-          const unsigned long long bm = __ballot(pass);
-          const int c = __popcll(bm);
-          if (c > 0) {
-            if (cur.used + c > cur.cap && !cur.full) {
-              cursor_close(cur, done, T);
-              cursor_open(cur, T, counters);
-              done = 0;
-            }
-            if (cur.cap > 0) {
-              if (pass) {
-                const int slot = cur.start + cur.used + __popcll(bm & lanemask_lt());
-                T.trips[2 * slot] = f;
-                T.trips[2 * slot + 1] = (int32_t)((uint32_t)j0 | ((uint32_t)j1 << 8) | ((uint32_t)j2 << 16));
-              }
-              cur.used += c;
-            }
-          }
-          total += c;
+        const unsigned long long bm = __ballot(pass);
+        if (pass) L.sjoin[nq + __popcll(bm & lanemask_lt())] = e | ((uint32_t)i0 << 16);
+        nq += __popcll(bm);
+        if (nq >= kWave) {
+          __syncthreads();
+          test(kWave);
+          const int rem = nq - kWave;
+          const uint32_t v = lane < rem ? L.sjoin[kWave + lane] : 0u;
+          __syncthreads();
+          if (lane < rem) L.sjoin[lane] = v;
+          __syncthreads();
+          nq = rem;
         }
-        __syncthreads();
       }
     };
     // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
@@ -407,6 +417,7 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       }
     }
     if (npend > 0) { __syncthreads(); join(npend); }
+    if (nq > 0) { __syncthreads(); test(nq); }
   }
   const bool ovf = total > C.max_trip;
   if (lane == 0) {
