@@ -125,6 +125,22 @@ __device__ inline uint64_t lanemask_lt() {
   return lane ? (~0ull >> (64u - lane)) : 0ull;
 }
 
+// Makes the values available in registers at this point: the loads that
+// produce them are issued here, together, rather than sunk by the compiler
+// into the branches that first use them (each such load would cost the wave
+// another memory round trip).  Emits no instruction.
+template <class A, class B, class C, class D, class E>
+__device__ inline void materialize(const A& a, const B& b, const C& c, const D& d, const E& e) {
+  asm volatile("" ::"v"(a), "v"(b), "v"(c), "v"(d), "v"(e));
+}
+template <class A, class B, class C, class D, class E, class F>
+__device__ inline void materialize(const A& a, const B& b, const C& c, const D& d, const E& e, const F& f) {
+  asm volatile("" ::"v"(a), "v"(b), "v"(c), "v"(d), "v"(e), "v"(f));
+}
+__device__ inline void materialize(float a, float b, float c, float d, float e, float f, float g, float h, float i) {
+  asm volatile("" ::"v"(a), "v"(b), "v"(c), "v"(d), "v"(e), "v"(f), "v"(g), "v"(h), "v"(i));
+}
+
 // ------------------------------------------------------------- cut tests
 // Each test decides in float32 when the value lies outside a bound of its own
 // rounding error around the window edges, and otherwise re-evaluates in
@@ -497,6 +513,7 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
   const float x0 = X[g0], y0 = Y[g0], z0 = Z[g0];
   const float x1 = X[g1], y1 = Y[g1], z1 = Z[g1];
   const float x2 = X[g2], y2 = Y[g2], z2 = Z[g2];
+  materialize(x0, y0, z0, x1, y1, z1, x2, y2, z2);
   const Fit<T> f1 = fit_triplet<T>(x0, y0, z0, x1, y1, z1, x2, y2, z2, C);
   if (!f1.ok) return (F32 && f1.c.cross != 0.0) ? -1 : 0;
   T px = 0, py = 0, pz = 0;
@@ -506,16 +523,14 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
   if (!reach) return 0;
   T best = (T)1e30, second = (T)1e30;
   int ib = -1;
+  float bx = 0.f, by = 0.f, bz = 0.f;   // the nearest hit so far
   auto consider = [&](float x, float y, float z, int g) {
     const T dx = (T)x - px, dy = (T)y - py, dz = (T)z - pz;
     const T d2 = dx * dx + dy * dy + dz * dz;
-    if (d2 < best) { second = best; best = d2; ib = g; }
+    if (d2 < best) { second = best; best = d2; ib = g; bx = x; by = y; bz = z; }
     else if (d2 < second) second = d2;
   };
-  // layer-3 hits in order, four at a time with 16-byte loads (dword-aligned
-  // addresses; all four inside [b3, b4)), then the rest one by one
-  int g = b3;
-  for (; g + 4 <= b4; g += 4) {
+  auto quad = [&](int g) {   // hits g .. g+3, all inside [b3, b4); 16-byte loads at dword-aligned addresses
     float4 vx, vy, vz;
     __builtin_memcpy(&vx, X + g, sizeof(float4));
     __builtin_memcpy(&vy, Y + g, sizeof(float4));
@@ -524,15 +539,28 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
     consider(vx.y, vy.y, vz.y, g + 1);
     consider(vx.z, vy.z, vz.z, g + 2);
     consider(vx.w, vy.w, vz.w, g + 3);
+  };
+  // layer-3 hits in order: four at a time, then the last 0..3 with their
+  // loads issued together (one memory round trip for the tail)
+  int g = b3;
+  for (; g + 4 <= b4; g += 4) quad(g);
+  {
+    const int m = b4 - g;
+    float tx[3] = {0.f, 0.f, 0.f}, ty[3] = {0.f, 0.f, 0.f}, tz[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k < m) { tx[k] = X[g + k]; ty[k] = Y[g + k]; tz[k] = Z[g + k]; }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k < m) consider(tx[k], ty[k], tz[k], g + k);
   }
-  for (; g < b4; ++g) consider(X[g], Y[g], Z[g], g);
   if (ib < 0) return 0;
   if (F32 && second < (T)1e29) {
     const T eps = (T)1e-3;   // bound on the float32 error of the predicted point [mm]
     if (second - best <= (T)2 * eps * (m_sqrt(best) + m_sqrt(second)) + (T)1e-5 * second) return -1;
   }
   g3 = ib;
-  const Fit<T> f2 = fit_triplet<T>(x1, y1, z1, x2, y2, z2, X[ib], Y[ib], Z[ib], C);
+  const Fit<T> f2 = fit_triplet<T>(x1, y1, z1, x2, y2, z2, bx, by, bz, C);
   if (!f2.ok) return (F32 && f2.c.cross != 0.0) ? -1 : 0;
   if (f2.c.sgn != f1.c.sgn) return 0;
   combine(f1, f2, kbar, chi2);
@@ -596,36 +624,42 @@ __device__ inline void emit_result(bool active, int r, int e, int f, int i3, flo
   }
 }
 
-__device__ inline void triplet_hits(const int32_t* __restrict__ lo, int f, uint32_t pk, int& g0, int& g1, int& g2,
-                                    int& b3, int& b4) {
-  g0 = lo[4 * f] + (int)(pk & 0xff);
-  g1 = lo[4 * f + 1] + (int)((pk >> 8) & 0xff);
-  g2 = lo[4 * f + 2] + (int)((pk >> 16) & 0xff);
-  b3 = lo[4 * f + 3];
-  b4 = lo[4 * f + 4];
+// Global hit indices of a list entry (frame f, packed frame-local indices pk)
+// and the frame's layer-3 range.
+struct EntryHits {
+  int g0, g1, g2, b3, b4;
+};
+
+__device__ inline EntryHits entry_hits(const int32_t* __restrict__ lo, int f, uint32_t pk) {
+  return EntryHits{lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
+                   lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3], lo[4 * f + 4]};
 }
 
-// Track reconstruction of one list entry (frame f, packed indices pk) in T;
-// i3 is the frame-local layer-3 hit of an accepted track.
+// A list entry of T: {frame, packed frame-local indices}, one 8-byte load.
+__device__ inline int2 list_entry(const TripList& T, int e) {
+  return *reinterpret_cast<const int2*>(T.trips + 2 * e);
+}
+
+// Track reconstruction of one list entry with hits h; i3 is the frame-local
+// layer-3 hit of an accepted track.
 template <class T>
 __device__ inline int fit_entry(const float* __restrict__ X, const float* __restrict__ Y,
-                                const float* __restrict__ Z, const int32_t* __restrict__ lo, const Consts& C, int f,
-                                uint32_t pk, int& i3, T& kb, T& c2) {
-  int g0, g1, g2, b3, b4, g3 = -1;
-  triplet_hits(lo, f, pk, g0, g1, g2, b3, b4);
-  const int r = track_eval<T>(X, Y, Z, g0, g1, g2, b3, b4, C, g3, kb, c2);
-  i3 = g3 >= 0 ? g3 - b3 : 0;
+                                const float* __restrict__ Z, const EntryHits& h, const Consts& C, int& i3, T& kb,
+                                T& c2) {
+  int g3 = -1;
+  const int r = track_eval<T>(X, Y, Z, h.g0, h.g1, h.g2, h.b3, h.b4, C, g3, kb, c2);
+  i3 = g3 >= 0 ? g3 - h.b3 : 0;
   return r;
 }
 
 // ------------------------------------------------------------ slice tables
-// The non-empty 64-entry slices of the granted chunks, packed as
-// chunk * 64 + slice (a chunk holds at most kMaxChunk = 64 * 64 entries).
-// fit: slices of [fitted, count), the entries k_tracks fits; all: slices of
-// [0, count).  counters[9] and counters[10] hold their lengths.
+// The non-empty slices of at most 64 entries of the granted chunks, each as
+// {first entry index, entry count}.  fit: slices of [fitted, count) of each
+// chunk, the entries k_tracks fits; all: slices of [0, count).  counters[9]
+// and counters[10] hold their lengths.
 struct Slices {
-  int32_t* fit;
-  int32_t* all;
+  int2* fit;
+  int2* all;
 };
 
 // Sums of a and b over a block of 256 threads (all threads get them).
@@ -695,8 +729,17 @@ k_splace(TripList T, Slices S, const int32_t* __restrict__ blk, int32_t* __restr
     __syncthreads();
   }
   const int of = bf + tmp[threadIdx.x] - nf, oa = ba + tmp[256 + threadIdx.x] - na;
-  for (int j = 0; j < nf; ++j) S.fit[of + j] = c * kWave + j;
-  for (int j = 0; j < na; ++j) S.all[oa + j] = c * kWave + j;
+  if (nf > 0 || na > 0) {
+    const int start = T.chunks[4 * c], n = T.chunks[4 * c + 1], from = T.chunks[4 * c + 2];
+    for (int j = 0; j < nf; ++j) {
+      const int t = from + j * kWave;
+      S.fit[of + j] = make_int2(start + t, min(kWave, n - t));
+    }
+    for (int j = 0; j < na; ++j) {
+      const int t = j * kWave;
+      S.all[oa + j] = make_int2(start + t, min(kWave, n - t));
+    }
+  }
 }
 
 // Float32 track reconstruction of the entries [fitted, count) of every
@@ -708,18 +751,18 @@ k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* 
          TrackOut O, int32_t* __restrict__ counters) {
   const int ns = counters[9];
   for (int v = blockIdx.x; v < ns; v += gridDim.x) {
-    const int pkd = S.fit[v];
-    const int32_t* row = T.chunks + 4 * (pkd / kWave);
-    const int start = row[0], n = row[1], from = row[2];
-    const int t = from + (pkd % kWave) * kWave + (int)threadIdx.x;
-    const bool active = t < n;
-    const int e = start + t;
+    const int2 sl = S.fit[v];
+    const bool active = (int)threadIdx.x < sl.y;
+    const int e = sl.x + (int)threadIdx.x;
     int r = 0, f = 0, i3 = 0;
     float kb = 0.f, c2 = 0.f;
     if (active) {
-      f = T.trips[2 * e];
-      if (!(flags[f] & MU3E_TRIPLET_OVF))
-        r = fit_entry<float>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kb, c2);
+      const int2 en = list_entry(T, e);
+      f = en.x;
+      const uint32_t fl = flags[f];
+      const EntryHits h = entry_hits(lo, f, (uint32_t)en.y);
+      materialize(fl, h.g0, h.g1, h.g2, h.b3, h.b4);   // one round trip for the flag and the offsets
+      if (!(fl & MU3E_TRIPLET_OVF)) r = fit_entry<float>(X, Y, Z, h, C, i3, kb, c2);
     }
     emit_result(active, r, e, f, i3, kb, c2, O, counters);
   }
@@ -753,8 +796,11 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
     int r = 0, f = 0, i3 = 0;
     float kb = 0.f, c2 = 0.f;
     if (active) {
-      f = T.trips[2 * e];
-      r = fit_entry<float>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kb, c2);
+      const int2 en = list_entry(T, e);
+      f = en.x;
+      const EntryHits h = entry_hits(lo, f, (uint32_t)en.y);
+      materialize(h.g0, h.g1, h.g2, h.b3, h.b4);
+      r = fit_entry<float>(X, Y, Z, h, C, i3, kb, c2);
     }
     emit_result(active, r, e, f, i3, kb, c2, O, counters);
     done += k;
@@ -812,10 +858,13 @@ k_tracks_redo(const float* __restrict__ X, const float* __restrict__ Y, const fl
   const int n = min(counters[5], O.redo_cap);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int e = O.redo[t];
-    const int f = T.trips[2 * e];
+    const int2 en = list_entry(T, e);
+    const int f = en.x;
     int i3 = 0;
     double kd = 0, cd = 0;
-    const int r = fit_entry<double>(X, Y, Z, lo, C, f, (uint32_t)T.trips[2 * e + 1], i3, kd, cd);
+    const EntryHits h = entry_hits(lo, f, (uint32_t)en.y);
+    materialize(h.g0, h.g1, h.g2, h.b3, h.b4);
+    const int r = fit_entry<double>(X, Y, Z, h, C, i3, kd, cd);
     store_result(O.res, e, r == 1 ? TR_ACCEPT : TR_REJECT, i3, (float)kd, (float)cd);
     if (r == 1) tally_track(O, f, e, (float)kd);
   }
@@ -1289,12 +1338,9 @@ k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* _
   if (counters[11] == 0) return;   // every candidate frame's tracks are in its slot row
   const int ns = counters[10];
   for (int v = blockIdx.x; v < ns; v += gridDim.x) {
-    const int pkd = S.all[v];
-    const int32_t* row = T.chunks + 4 * (pkd / kWave);
-    const int start = row[0], n = row[1];
-    const int t = (pkd % kWave) * kWave + (int)threadIdx.x;
-    if (t >= n) continue;
-    const int e = start + t;
+    const int2 sl = S.all[v];
+    if ((int)threadIdx.x >= sl.y) continue;
+    const int e = sl.x + (int)threadIdx.x;
     if (res[4 * e] != TR_ACCEPT) continue;
     const int f = T.trips[2 * e];
     const int b = vbase[f];
@@ -1481,8 +1527,8 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.chunks = o; o += align256((size_t)(tc / kMinChunk + 1) * 4 * sizeof(int32_t));
   L.trips = o; o += align256((size_t)tc * 2 * sizeof(int32_t));
   L.res = o; o += align256((size_t)tc * 4 * sizeof(int32_t));
-  L.sfit = o; o += align256((size_t)slice_capacity(tc) * sizeof(int32_t));
-  L.sall = o; o += align256((size_t)slice_capacity(tc) * sizeof(int32_t));
+  L.sfit = o; o += align256((size_t)slice_capacity(tc) * sizeof(int2));
+  L.sall = o; o += align256((size_t)slice_capacity(tc) * sizeof(int2));
   L.sblk = o; o += align256((size_t)2 * ((tc / kMinChunk + 1 + 255) / 256) * sizeof(int32_t));
   L.redo = o; o += align256((size_t)(kc / 8 + 1024) * sizeof(int32_t));
   L.vt = o; o += align256((size_t)kc * sizeof(VTrack));
@@ -1547,8 +1593,8 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.chunks = reinterpret_cast<int32_t*>(ws + L.chunks);
   W.trips = reinterpret_cast<int32_t*>(ws + L.trips);
   W.res = reinterpret_cast<int32_t*>(ws + L.res);
-  W.S.fit = reinterpret_cast<int32_t*>(ws + L.sfit);
-  W.S.all = reinterpret_cast<int32_t*>(ws + L.sall);
+  W.S.fit = reinterpret_cast<int2*>(ws + L.sfit);
+  W.S.all = reinterpret_cast<int2*>(ws + L.sall);
   W.sblk = reinterpret_cast<int32_t*>(ws + L.sblk);
   W.redo = reinterpret_cast<int32_t*>(ws + L.redo);
   W.vt = reinterpret_cast<VTrack*>(ws + L.vt);
