@@ -15,6 +15,11 @@ FLAGS = [
     "-mcode-object-version=5",
     # no packed float32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # float32 division and square root by the hardware reciprocal / root
+    # (within 2 ulp) instead of the correctly rounded sequences: the float32
+    # paths decide nothing within a few ulp of an edge (their margins are
+    # orders of magnitude wider), and the track fit is bound by these sequences
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wall",
 ]
 

@@ -1644,7 +1644,10 @@ void launch_tracks(const mu3e_hits_t& h, const Consts& C, int cus, const WsView&
   const int nbk = (int)(((int64_t)T.capacity / T.chunk + 1 + 255) / 256);
   hipLaunchKernelGGL(k_scount, dim3(nbk), dim3(256), 0, stream, T, W.sblk, W.counters);
   hipLaunchKernelGGL(k_splace, dim3(nbk), dim3(256), 0, stream, T, W.S, W.sblk, W.counters);
-  hipLaunchKernelGGL(k_tracks, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, flags, T,
+  // many more waves than fit at once: the slices outnumber them only a few
+  // times, and the hardware refills finished waves, which balances better
+  // than a ragged last round of a resident grid
+  hipLaunchKernelGGL(k_tracks, dim3(cus * 128), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, flags, T,
                      W.S, O, W.counters);
   if (after_fits) (void)hipEventRecord(after_fits, stream);
   hipLaunchKernelGGL(k_tracks_redo, dim3(cus), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, T, O,

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mu3e_atan.hpp"
+
 namespace mu3e {
 
 constexpr double kCLight = 0.299792458;   // p[MeV] = kCLight * B[T] * R[mm]
@@ -93,11 +95,18 @@ __host__ __device__ inline Circle<T> circle3(double x0, double y0, double z0, do
   // The absolute value selects the minor arc.
   const double acr = c.cross > 0.0 ? c.cross : -c.cross;
   const double n1 = fabs(bb + ee - aa), n2 = fabs(aa + ee - bb);
-  c.cot1 = (T)(n1 / (2.0 * acr));
-  c.cot2 = (T)(n2 / (2.0 * acr));
-  // Phi_k = 2 atan2(2 area, |b^2 + c^2 - a^2|) (minor arc, in [0, pi])
-  c.phi1 = 2.0 * atan2(2.0 * acr, n1);
-  c.phi2 = 2.0 * atan2(2.0 * acr, n2);
+  if (sizeof(T) == 4) {   // float32 quotients of the exact float64 terms
+    const float a2 = (float)(2.0 * acr);
+    c.cot1 = (T)((float)n1 / a2);
+    c.cot2 = (T)((float)n2 / a2);
+  } else {
+    c.cot1 = (T)(n1 / (2.0 * acr));
+    c.cot2 = (T)(n2 / (2.0 * acr));
+  }
+  // Phi_k = 2 atan2(2 area, |b^2 + c^2 - a^2|) (minor arc, in [0, pi]);
+  // both arguments are non-negative
+  c.phi1 = 2.0 * atan2_q1(2.0 * acr, n1);
+  c.phi2 = 2.0 * atan2_q1(2.0 * acr, n2);
   const double dz1 = z1 - z0, dz2 = z2 - z1;
   c.z1 = (T)dz1;
   c.z2 = (T)dz2;
