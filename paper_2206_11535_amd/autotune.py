@@ -36,9 +36,11 @@ def candidates():
 
 
 def source_tag() -> str:
+    """Hash of the kernel sources and the build flags (build.py)."""
     h = hashlib.sha256()
-    for name in ("mu3e.hip", "mu3e_math.hpp"):
-        with open(os.path.join(PKG, "csrc", name), "rb") as f:
+    names = sorted(n for n in os.listdir(os.path.join(PKG, "csrc")) if n.endswith((".hip", ".hpp")))
+    for path in [os.path.join(PKG, "csrc", n) for n in names] + [os.path.join(PKG, "build.py")]:
+        with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:10]
 
