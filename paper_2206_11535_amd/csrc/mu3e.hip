@@ -745,7 +745,7 @@ k_splace(TripList T, Slices S, const int32_t* __restrict__ blk, int32_t* __restr
 // Float32 track reconstruction of the entries [fitted, count) of every
 // chunk, one wave per 64-entry slice (dealt cyclically to the grid);
 // candidates the float32 arithmetic cannot decide go to the float64 list.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
 k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
          const int32_t* __restrict__ lo, Consts C, const uint32_t* __restrict__ flags, TripList T, Slices S,
          TrackOut O, int32_t* __restrict__ counters) {
@@ -894,8 +894,8 @@ __device__ inline bool vtrack_make(const float* __restrict__ X, const float* __r
   v.rbar = 1.0 / fabs(kbar);
   v.p = kCLight * (double)C.b * v.rbar;
   v.E = sqrt(v.p * v.p + kMassE * kMassE);
-  v.cth = cos(a.th1);
-  const double sth = sin(a.th1);
+  v.cth = a.cth1;
+  const double sth = a.sth1;
   v.hx = X[g0]; v.hy = Y[g0]; v.hz = Z[g0];
   const double dx = (double)X[g1] - v.hx, dy = (double)Y[g1] - v.hy;
   const double d = sqrt(dx * dx + dy * dy);
@@ -915,7 +915,7 @@ __device__ inline bool vtrack_make(const float* __restrict__ X, const float* __r
 // the point q, in [0, 2 pi).
 __device__ inline double back_turn(const VTrack& t, double qx, double qy) {
   const double vx = t.hx - t.cx, vy = t.hy - t.cy, wx = qx - t.cx, wy = qy - t.cy;
-  double a = atan2(vx * wy - vy * wx, vx * wx + vy * wy);   // counter-clockwise h0 -> q
+  double a = atan2_full(vx * wy - vy * wx, vx * wx + vy * wy);   // counter-clockwise h0 -> q
   if (t.q < 0) a = -a;                                       // backwards of a clockwise track is ccw
   if (a < 0) a += 2.0 * kPiD;
   return a;
@@ -1361,8 +1361,10 @@ struct RangeId {
 
 // One wave per candidate frame.  A frame with at most kTrackSlots tracks
 // refits them here (lanes over its slot row) into LDS; a larger one uses the
-// table slice filled by k_vprep.
-__global__ void __launch_bounds__(64)
+// table slice filled by k_vprep.  Each frame is a long chain of dependent
+// float64 work on few lanes, so two waves per SIMD (at most 256 registers,
+// a few spilled) beat one wave with every value in registers.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
                const int32_t* __restrict__ lo, Consts C, TripList T, const int32_t* __restrict__ res,
                const int32_t* __restrict__ tslot, const int32_t* __restrict__ counters,
@@ -1668,9 +1670,9 @@ void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const 
   hipLaunchKernelGGL(k_vprep, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets, C, T,
                      W.S, W.res, counts, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok);
   if (ev) (void)hipEventRecord(ev[3], stream);
-  // one wave per SIMD is resident (float64-heavy, many registers): no more
-  // blocks than that, so that every candidate frame starts at once
-  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 4), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets,
+  // two waves per SIMD are resident (float64-heavy, many registers): no
+  // more blocks than that, so that every candidate frame starts at once
+  hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets,
                      C, T, W.res, W.tslot, W.counters, W.cand, W.vbase, W.vpos, vcap, W.vt, W.vok, flags, counts,
                      vtx);
   if (ev) (void)hipEventRecord(ev[4], stream);

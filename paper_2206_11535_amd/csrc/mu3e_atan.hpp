@@ -14,7 +14,7 @@
 
 namespace mu3e {
 
-// atan2(y, x) for x >= 0, y >= 0 of magnitude within the float32 range, in
+// atan2(y, x) for finite x >= 0, y >= 0 (magnitudes 1e-90 .. 1e90), in
 // [0, pi/2]; 0 when both are 0.  One division reduces the argument to
 // |u| <= tan(pi/8): u = min/max, or
 // (min - max)/(min + max) with atan(min/max) = pi/4 + atan(u) above tan(pi/8);
@@ -27,8 +27,12 @@ MU3E_HD inline double atan2_q1(double y, double x) {
   const bool swap = y > x;
   const double hi = swap ? y : x, lo = swap ? x : y;   // 0 <= lo <= hi
   const bool mid = lo > 0.41421356237309503 * hi;      // lo / hi > tan(pi/8)
-  const double num = mid ? lo - hi : lo;
-  const double den = mid ? lo + hi : (hi > 0.0 ? hi : 1.0);
+  double num = mid ? lo - hi : lo;
+  double den = mid ? lo + hi : (hi > 0.0 ? hi : 1.0);
+  // the quotient is scale-free: bring den into the float32 range of the seed
+  const double sc = den < 1e-30 ? 0x1p+200 : (den > 1e30 ? 0x1p-200 : 1.0);
+  num *= sc;
+  den *= sc;
   // num / den with a float32 reciprocal refined by two Newton steps and a
   // final residual correction (within an ulp, no float64 division)
   const double r0 = (double)(1.0f / (float)den);
@@ -50,6 +54,16 @@ MU3E_HD inline double atan2_q1(double y, double x) {
   double a = fma(u * s, p, u);
   if (mid) a += 0.78539816339744830962;                  // pi/4
   return swap ? 1.5707963267948966192 - a : a;           // pi/2 - atan(x/y)
+}
+
+// atan2(y, x) over all four quadrants from the first-quadrant one: the
+// angle of (|x|, |y|), reflected to x < 0 and signed by y (the sign of a
+// zero y decides, as for the C library: +-0 or +-pi).  Finite inputs of
+// magnitude 1e-90 .. 1e90 (or zero).
+MU3E_HD inline double atan2_full(double y, double x) {
+  const double a = atan2_q1(fabs(y), fabs(x));
+  const double b = signbit(x) ? 3.14159265358979323846 - a : a;
+  return signbit(y) ? -b : b;
 }
 
 }  // namespace mu3e

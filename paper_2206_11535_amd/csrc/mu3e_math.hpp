@@ -41,7 +41,7 @@ struct Consts {
 __host__ __device__ inline float m_sqrt(float x) { return sqrtf(x); }
 __host__ __device__ inline double m_sqrt(double x) { return sqrt(x); }
 __host__ __device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
-__host__ __device__ inline double m_atan2(double y, double x) { return atan2(y, x); }
+__host__ __device__ inline double m_atan2(double y, double x) { return atan2_full(y, x); }
 __host__ __device__ inline float m_sin(float x) { return sinf(x); }
 __host__ __device__ inline double m_sin(double x) { return sin(x); }
 __host__ __device__ inline float m_cos(float x) { return cosf(x); }
@@ -157,6 +157,7 @@ __host__ __device__ inline T phicot_minus_2(T phi, T cot_half) {
 template <class T>
 struct Fit {
   T kappa, s2kappa, chi2, rstar, s2r, th1, th2, phi2;
+  T sth1, cth1;   // sin and cos of th1, from the arc length and step (no arctangent)
   Circle<T> c;
   bool ok;
 };
@@ -169,7 +170,7 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
   f.ok = false;
   if (f.c.cross == 0.0) return f;
   const T rho = f.c.rho;
-  T phi[2], th[2], Rk[2], al[2], be[2];
+  T phi[2], th[2], sth[2], cth[2], Rk[2], al[2], be[2];
   const T ck[2] = {f.c.cot1, f.c.cot2};
   const T zk[2] = {f.c.z1, f.c.z2};
   phi[0] = (T)f.c.phi1;
@@ -179,12 +180,13 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
     const T cot = ck[k];                                     // cot(Phi/2)
     const T arc = rho * phi[k];                              // transverse arc length
     const T len = m_sqrt(arc * arc + zk[k] * zk[k]);
-    th[k] = m_atan2(arc, zk[k]);
-    const T sth = arc / len;                                 // sin(theta_k)
-    Rk[k] = rho / sth;
+    th[k] = m_atan2(arc, zk[k]);                             // output only
+    sth[k] = arc / len;                                      // sin(theta_k)
+    cth[k] = zk[k] / len;                                    // cos(theta_k)
+    Rk[k] = rho / sth[k];
     const T D = rho * rho * cot + (T)2 * zk[k] * zk[k] / (phi[k] * phi[k] * phi[k]);
     al[k] = -(T)2 * Rk[k] / D;
-    be[k] = zk[k] * rho * rho * phicot_minus_2(phi[k], cot) / (D * Rk[k] * Rk[k] * phi[k] * phi[k] * sth);
+    be[k] = zk[k] * rho * rho * phicot_minus_2(phi[k], cot) / (D * Rk[k] * Rk[k] * phi[k] * phi[k] * sth[k]);
   }
   const T Rbar = (T)0.5 * (Rk[0] + Rk[1]);
   // theta_2 - theta_1 = atan2(rho K, rho^2 Phi1 Phi2 + z1 z2) and
@@ -198,7 +200,11 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
   const T bphi = -(T)0.5 * (al[0] + al[1]);
   const T th0 = dth - dR * (be[1] + be[0]);
   const T bth = be[1] - be[0];
-  const T sn = m_sin((T)0.5 * (th[0] + th[1]));
+  // sin of the mean polar angle from the sines and cosines of the two:
+  // sin th1 + sin th2 = 2 sin(mean) cos(half difference), and the half
+  // difference's cosine is sqrt((1 + cos(th1 - th2)) / 2), both well
+  // conditioned as th1 ~ th2 (no arctangent or sine evaluated)
+  const T sn = (sth[0] + sth[1]) / m_sqrt((T)2 * ((T)1 + cth[0] * cth[1] + sth[0] * sth[1]));
   const T s2 = sn * sn;
   const T p = (T)kCLight * (T)C.b * Rbar;
   const T X = (T)C.xx0 / sn;
@@ -215,6 +221,8 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
   f.s2kappa = f.s2r / (r2 * r2);
   f.th1 = th[0];
   f.th2 = th[1];
+  f.sth1 = sth[0];
+  f.cth1 = cth[0];
   f.phi2 = phi[1];
   f.ok = f.rstar > (T)0 && f.chi2 == f.chi2;
   return f;

@@ -1,7 +1,8 @@
 """Host checks of the kernels' own float64 arctangent (mu3e_atan.hpp), built
 with the host C++ compiler: it must agree with the C library's atan2 to a
-few units in the last place on the first quadrant, where the triplet fit
-takes its arc angles (Section IV-B)."""
+few units in the last place, on the first quadrant (the arc angles of the
+triplet fit, Section IV-B) and on all four (turning angles of the vertex
+stage, Section IV-C), signed zeros included."""
 import os
 import shutil
 import subprocess
@@ -18,41 +19,52 @@ PROGRAM = r"""
 #include <stdlib.h>
 #include <string.h>
 static int64_t ord(double v) { int64_t i; memcpy(&i, &v, 8); return i; }
+static int64_t ulps(double a, double b) {
+  if (a == b) return 0;                       // also +0 == -0
+  if (signbit(a) != signbit(b)) return 1LL << 62;
+  return llabs(ord(a) - ord(b));
+}
 int main() {
   srand48(7);
-  int64_t worst = 0;
+  int64_t worst_q1 = 0, worst_full = 0;
   for (int k = 0; k < 2000000; ++k) {
     double y = drand48(), x = drand48();
     if (k % 4 == 1) y *= 1e-6;            // nearly flat
     if (k % 4 == 2) x *= 1e-6;            // nearly vertical
     if (k % 4 == 3) {                     // wide exponent range
-      y = ldexp(y, (int)(drand48() * 80) - 40);
-      x = ldexp(x, (int)(drand48() * 80) - 40);
+      const int e = (int)(drand48() * 560) - 280;
+      y = ldexp(y, e + (int)(drand48() * 20) - 10);
+      x = ldexp(x, e);
     }
-    const int64_t d = llabs(ord(mu3e::atan2_q1(y, x)) - ord(atan2(y, x)));
-    if (d > worst) worst = d;
+    const int64_t d = ulps(mu3e::atan2_q1(y, x), atan2(y, x));
+    if (d > worst_q1) worst_q1 = d;
+    const double sy = (k & 1) ? -y : y, sx = (k & 2) ? -x : x;   // all quadrants
+    const int64_t e = ulps(mu3e::atan2_full(sy, sx), atan2(sy, sx));
+    if (e > worst_full) worst_full = e;
   }
-  // octant edges and special points
+  // octant edges, axes and signed zeros
   const double tp8 = 0.41421356237309503;
   const double pts[][2] = {{0.0, 0.0}, {0.0, 1.0}, {1.0, 0.0}, {1.0, 1.0}, {tp8, 1.0},
-                           {nextafter(tp8, 1.0), 1.0}, {1.0, tp8}, {1.0, 3e-30}};
+                           {nextafter(tp8, 1.0), 1.0}, {1.0, tp8}, {1.0, 3e-30}, {0.0, -1.0},
+                           {-0.0, -1.0}, {-0.0, 1.0}, {-1.0, 0.0}, {-1.0, -1.0}, {1e-80, -1.0}};
   int64_t edge = 0;
   for (const auto& p : pts) {
-    const int64_t d = llabs(ord(mu3e::atan2_q1(p[0], p[1])) - ord(atan2(p[0], p[1])));
+    const int64_t d = ulps(mu3e::atan2_full(p[0], p[1]), atan2(p[0], p[1]));
     if (d > edge) edge = d;
   }
-  printf("%lld %lld\n", (long long)worst, (long long)edge);
+  printf("%lld %lld %lld\n", (long long)worst_q1, (long long)worst_full, (long long)edge);
   return 0;
 }
 """
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="no host C++ compiler")
-def test_atan2_q1_against_libm(tmp_path):
+def test_atan2_against_libm(tmp_path):
     src = tmp_path / "t.cpp"
     src.write_text(PROGRAM)
     exe = tmp_path / "t"
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", CSRC, "-o", str(exe), str(src), "-lm"])
-    worst, edge = map(int, subprocess.check_output([str(exe)], text=True).split())
-    assert worst <= 2, worst
+    worst_q1, worst_full, edge = map(int, subprocess.check_output([str(exe)], text=True).split())
+    assert worst_q1 <= 2, worst_q1
+    assert worst_full <= 2, worst_full
     assert edge <= 1, edge
