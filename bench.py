@@ -5,10 +5,15 @@ Vertex Fit) over one batch of synthetic frames already resident in HBM.
 Workload: the nominal rate, 100,000 frames of 64 ns at 1e8 mu/s
 (Poisson(6.4) Michel decays per frame, 5 noise hits per layer, signal in 1 %
 of frames).  Both forms run on it: the plain per-frame kernels and the
-batched persistent form (one hipGraph launch, autotuned shape); `value` is
-the batched form.  Optional legs: the mixed-rate 1,000,000-frame batch
-(both forms, identical outputs required) and the alignment gradient.
-Prints one JSON line.
+batched persistent form (one hipGraph launch, autotuned shape).  `value` is
+the batched form with `--inflight` batches in flight, as a continuous stream
+of batches is processed: each of that many distinct batches (different
+seeds, same workload) has its own plan and stream, and step k runs batch
+k mod n, so one batch's latency-bound stages overlap another's cuts.  The
+same form with one batch in flight is reported alongside.  Optional legs:
+the mixed-rate 1,000,000-frame batch (both forms, one batch in flight,
+identical outputs required) and the alignment gradient.  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -95,7 +100,7 @@ def cpu_baseline(fs, params, min_seconds=10.0):
     from oracle import oracle
     threads = oracle.threads_used(0)
     done, secs, reps = 0, 0.0, 0
-    while secs < min_seconds and reps < 20:
+    while secs < min_seconds and reps < 60:
         r = oracle.run(fs, params, lists=False)
         secs += r.seconds
         done += fs.n_frames
@@ -133,6 +138,33 @@ def time_steps(sel, dh, stream, hip, steps, warmup, staged=False):
     if staged:
         stage = np.mean([[hip.elapsed(ev[k][s], ev[k][s + 1]) for s in range(4)] for k in range(steps)], axis=0)
     return float(np.mean(step_ms)), stage, wall
+
+
+def time_inflight(plans, streams, hip, steps, warmup):
+    """Wall-clock ms per step with step k on plans[k % n] / streams[k % n]
+    (bracketed by device synchronisation), and the mean latency of one batch
+    (HIP events around its graph launch on its stream)."""
+    import torch
+    n = len(plans)
+    for k in range(warmup * n):
+        plans[k % n].run(None, streams[k % n])
+    torch.cuda.synchronize()
+    for pl in plans:
+        c = pl.counters()
+        if c[2] != 0:
+            raise RuntimeError(f"candidate lists overflowed the workspace: {c}")
+    ev = [hip.events(2) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        st = streams[k % n]
+        hip.record(ev[k][0], st)
+        plans[k % n].run(None, st)
+        hip.record(ev[k][1], st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = float(np.mean([hip.elapsed(e[0], e[1]) for e in ev]))
+    return wall / steps * 1e3, lat, wall
 
 
 def fitted_triplets(sel, fs):
@@ -212,9 +244,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="also the mixed-rate 1,000,000-frame batch")
     ap.add_argument("--align", action="store_true", help="also the alignment gradient (misaligned frames)")
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="distinct batches in flight on their own streams for `value` (1: one at a time)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the HBM traffic counters)")
     a = ap.parse_args()
+    if a.inflight < 1:
+        ap.error("--inflight must be at least 1")
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {a.gpus} requested): frames are independent, so more GPUs "
               f"would each take a contiguous range of frames; that split is not built here", file=sys.stderr)
@@ -239,8 +275,29 @@ def main():
     (w, c, u, st), _, _ = autotune.tune(dh, p)
     batched = lib.BatchedSelector(dh, p, device=dev, waves_per_cu=w, frames_per_claim=c, fuse_fits=u,
                                   steal_percent=st)
-    ms_batched, _, wall = time_steps(batched, dh, stream, hip, a.steps, a.warmup)
+    ms_one, _, wall_one = time_steps(batched, dh, stream, hip, a.steps, a.warmup)
     identical = same_outputs(plain, batched)
+    # ---- the batched form with `inflight` distinct batches in flight
+    latency = ms_one
+    ms_batched, wall = ms_one, wall_one
+    inflight_equal = True
+    if a.inflight > 1:
+        plans, streams = [batched], [torch.cuda.Stream(dev)]
+        refs = []
+        for i in range(1, a.inflight):
+            fi = synth.generate(synth.CONFIGS[2], n_frames=a.frames, salt=i)
+            di = lib.to_device(fi, dev)
+            plans.append(lib.BatchedSelector(di, p, device=dev, waves_per_cu=w, frames_per_claim=c, fuse_fits=u,
+                                             steal_percent=st))
+            streams.append(torch.cuda.Stream(dev))
+            refs.append(lib.select_frames(di, p))
+        ms_batched, latency, wall = time_inflight(plans, streams, hip, a.steps, a.warmup)
+        torch.cuda.synchronize()
+        inflight_equal = same_outputs(plain, batched) and all(same_outputs(r, q) for r, q in zip(refs, plans[1:]))
+        Fb = [q.hits.n_frames for q in plans]
+        if len(set(Fb)) != 1:
+            raise RuntimeError(f"batches of different sizes in flight: {Fb}")
+        del refs
     # kernel durations: the same sequence launched eagerly with events around
     # the persistent kernel and the fit kernel, on the launch stream
     ev = [hip.events(4) for _ in range(a.steps)]
@@ -276,9 +333,13 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"nominal rate, {F} frames of 64 ns, Poisson(6.4) Michel decays + 5 noise "
                                f"hits/layer, signal in 1% of frames", "frames": F, "form": "batched",
+                   "batches_in_flight": a.inflight,
                    "waves_per_cu": batched.effective[0], "frames_per_claim": batched.effective[1],
                    "fused_fits": fused, "steal_percent": batched.effective[3]},
         "fitted_triplets_per_s": fitted / (ms_batched / 1e3),
+        "batch_latency_ms": latency,
+        "one_in_flight": {"value": F / (ms_one / 1e3), "ms_per_step": ms_one},
+        "inflight_equals_plain": inflight_equal,
         "plain": {"value": F / (ms_plain / 1e3), "ms_per_step": ms_plain,
                   "fitted_triplets_per_s": fitted / (ms_plain / 1e3),
                   "stage_ms": {s: float(v) for s, v in zip(STAGES, stage_ms)},

@@ -109,6 +109,32 @@ def test_empty_and_tiny_frames(lib):
     check(lib, fs, default_params(), "tiny frames")
 
 
+def test_batches_in_flight(lib):
+    """Distinct batches in flight on their own streams, as bench.py times
+    them: after three interleaved rounds every plan's outputs equal the plain
+    form on its own batch."""
+    import torch
+    p = default_params()
+    hs = [lib.to_device(synth.generate(2, n_frames=3000, salt=s)) for s in range(3)]
+    refs = [lib.select_frames(h, p) for h in hs]
+    torch.cuda.synchronize()
+    shapes = [(8, 4, 0, 0), (12, 4, 1, 25), (16, 8, 0, 50)]
+    plans = [lib.BatchedSelector(h, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=u, steal_percent=st)
+             for h, (w, c, u, st) in zip(hs, shapes)]
+    streams = [torch.cuda.Stream() for _ in plans]
+    print("case: three plans on three streams, three rounds", flush=True)
+    for _ in range(3):
+        for b, st in zip(plans, streams):
+            b.run(None, st)
+    torch.cuda.synchronize()
+    for k, (r, b) in enumerate(zip(refs, plans)):
+        fr, cr, vr = r.result()
+        fb, cb, vb = b.result()
+        assert np.array_equal(fr, fb) and np.array_equal(cr, cb), k
+        assert np.array_equal(np.nan_to_num(vr), np.nan_to_num(vb)), k
+        assert b.counters()[2] == 0
+
+
 def test_batched_empty_and_tiny(lib):
     """The batched form on a batch without frames, on one frame, and on the
     tiny frames above (every shape), against the plain form."""
