@@ -120,9 +120,13 @@ __device__ inline void cursor_open(Cursor& c, const TripList& T, int32_t* __rest
   c.full = start < 0;
 }
 
-__device__ inline uint64_t lanemask_lt() {
-  const unsigned lane = threadIdx.x & 63u;
-  return lane ? (~0ull >> (64u - lane)) : 0ull;
+// Wave ballot of a condition: the condition's lane mask as the compare
+// produced it (no detour through a 0/1 integer).
+__device__ inline unsigned long long ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+// Set bits of m below this lane (the lane's rank among the set lanes).
+__device__ inline int rank_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
 // Makes the values available in registers at this point: the loads that
@@ -225,7 +229,7 @@ __device__ inline bool cos_cut_wave(bool act, float x0, float y0, float x1, floa
                                     float hi, float Ra, float Rb) {
   const Verdict v = cos_test(x0, y0, x1, y1, invRR, lo, hi);
   bool pass = act && v.pass;
-  if (__ballot(act && v.amb) != 0ull) {
+  if (ballot(act && v.amb) != 0ull) {
     if (act && v.amb) pass = cos_refine(x0, y0, x1, y1, lo, hi, Ra, Rb);
   }
   return pass;
@@ -343,11 +347,11 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
       const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
       bool rpass = vr.pass;
-      if (__ballot(act && vr.amb) != 0ull) {   // rare: float64 where float32 cannot decide
+      if (ballot(act && vr.amb) != 0ull) {   // rare: float64 where float32 cannot decide
         if (act && vr.amb) rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
       }
       const bool pass = act && rpass;
-      const unsigned long long bm = __ballot(pass);
+      const unsigned long long bm = ballot(pass);
       const int c = __popcll(bm);
       if (c > 0) {
         if (cur.used + c > cur.cap && !cur.full) {
@@ -357,7 +361,7 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
         }
         if (cur.cap > 0) {
           if (pass) {
-            const int slot = cur.start + cur.used + __popcll(bm & lanemask_lt());
+            const int slot = cur.start + cur.used + rank_below(bm);
             T.trips[2 * slot] = f;
             T.trips[2 * slot + 1] = (int32_t)((uint32_t)j0 | ((uint32_t)j1 << 8) | ((uint32_t)j2 << 16));
           }
@@ -379,19 +383,24 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       unsigned long long w0 = have ? L.sm01[2 * i1] : 0ull, w1 = have ? L.sm01[2 * i1 + 1] : 0ull;
       const float z1 = L.sz[kMaxLayerHits + i1], z2 = L.sz[2 * kMaxLayerHits + i2];
       const float t12 = (z2 - z1) * C.inv12;
-      while (__ballot((w0 | w1) != 0ull) != 0ull) {
+      while (ballot((w0 | w1) != 0ull) != 0ull) {
+        // next partner, taken without a branch: the lowest set bit of the
+        // first non-empty mask word
         const bool has = (w0 | w1) != 0ull;
-        int i0 = 0;
-        if (w0) { i0 = __ffsll((long long)w0) - 1; w0 &= w0 - 1; }
-        else if (w1) { i0 = 64 + __ffsll((long long)w1) - 1; w1 &= w1 - 1; }
+        const bool in0 = w0 != 0ull;
+        const unsigned long long w = in0 ? w0 : w1;
+        const unsigned long long rest = w & (w - 1);
+        const int i0 = has ? (in0 ? 0 : 64) + (int)__builtin_ctzll(w) : 0;
+        w0 = in0 ? rest : w0;
+        w1 = in0 ? w1 : rest;
         const float z0 = L.sz[i0];
         const Verdict vd = dl_test(z0, z1, t12, C);
         bool pass = has && vd.pass;
-        if (__ballot(has && vd.amb) != 0ull) {   // rare: float64 where float32 cannot decide
+        if (ballot(has && vd.amb) != 0ull) {   // rare: float64 where float32 cannot decide
           if (has && vd.amb) pass = dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
         }
-        const unsigned long long bm = __ballot(pass);
-        if (pass) L.sjoin[nq + __popcll(bm & lanemask_lt())] = e | ((uint32_t)i0 << 16);
+        const unsigned long long bm = ballot(pass);
+        if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16);
         nq += __popcll(bm);
         if (nq >= kWave) {
           __syncthreads();
@@ -418,8 +427,8 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const bool pass = cos_cut_wave(act, L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1],
                                      L.sx[2 * kMaxLayerHits + i2], L.sy[2 * kMaxLayerHits + i2], C.invRR12,
                                      C.c12_lo, C.c12_hi, C.R[1], C.R[2]);
-      const unsigned long long bm = __ballot(pass);
-      if (pass) L.spend[npend + __popcll(bm & lanemask_lt())] = (uint32_t)i1 | ((uint32_t)i2 << 8);
+      const unsigned long long bm = ballot(pass);
+      if (pass) L.spend[npend + rank_below(bm)] = (uint32_t)i1 | ((uint32_t)i2 << 8);
       npend += __popcll(bm);
       if (npend >= kWave) {
         __syncthreads();
@@ -606,7 +615,7 @@ __device__ inline void tally_track(const TrackOut& O, int f, int e, float kb) {
 // undecided entries of the wave are queued with one atomic.
 __device__ inline void emit_result(bool active, int r, int e, int f, int i3, float kb, float c2,
                                    const TrackOut& O, int32_t* __restrict__ counters) {
-  const unsigned long long und = __ballot(active && r < 0);
+  const unsigned long long und = ballot(active && r < 0);
   int qbase = 0;
   if (und != 0ull) {
     if (threadIdx.x == 0) qbase = atomicAdd(&counters[5], __popcll(und));
@@ -614,7 +623,7 @@ __device__ inline void emit_result(bool active, int r, int e, int f, int i3, flo
   }
   if (!active) return;
   if (r < 0) {
-    const int q = qbase + __popcll(und & lanemask_lt());
+    const int q = qbase + rank_below(und);
     if (q < O.redo_cap) O.redo[q] = e;
     else atomicOr(&counters[2], ST_TRACK_FULL);
     store_result(O.res, e, TR_REDO, 0, 0.f, 0.f);
@@ -1126,9 +1135,9 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     const int t = j < n ? id(j) : -1;
     const bool ok = t >= 0 && vok[t];
     const bool ps = ok && vt[t].q > 0, ng = ok && vt[t].q < 0;
-    const unsigned long long mp = __ballot(ps), mn = __ballot(ng);
-    if (ps) spos[np + __popcll(mp & lanemask_lt())] = t;
-    if (ng) sneg[nn + __popcll(mn & lanemask_lt())] = t;
+    const unsigned long long mp = ballot(ps), mn = ballot(ng);
+    if (ps) spos[np + rank_below(mp)] = t;
+    if (ng) sneg[nn + rank_below(mn)] = t;
     np += __popcll(mp);
     nn += __popcll(mn);
   }
@@ -1179,7 +1188,7 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
         const double s = vt[ta].E + vt[tb].E + vt[te].E;
         ep = s >= elo && s <= ehi;
       }
-      if (__ballot(ep) == 0ull) continue;   // wave-uniform
+      if (ballot(ep) == 0ull) continue;   // wave-uniform
       VPoints P;
       int m = 0;
       if (ep && vertex_points(&vt[ta], &vt[tb], &vt[te], C, P)) m = vertex_combos(P);
@@ -1189,8 +1198,8 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
       int pos = 0, tot = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const unsigned long long mb = __ballot((nc >> b) & 1);
-        pos += __popcll(mb & lanemask_lt()) << b;
+        const unsigned long long mb = ballot((nc >> b) & 1);
+        pos += rank_below(mb) << b;
         tot += __popcll(mb) << b;
       }
       for (int c = 0; c < 8; ++c)
