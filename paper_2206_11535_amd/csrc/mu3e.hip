@@ -50,6 +50,7 @@ constexpr int kMaxChunk = 4096;
 constexpr int kMaxTripletCapacity = 1 << 30; // keeps the chunk bump counter within int32
 constexpr int kClaimRanges = 8;              // claim counters of the batched form,
 constexpr int kClaimStride = 1024;           // int32 apart (4 KiB)
+constexpr int kTallyOffset = 512;            // selected-triplet tallies: claims + k * kClaimStride + 512
 
 // counters: [0] triplets selected, [2] status bits, [3] candidate frames of
 // the vertex stage, [4] their track-table size, [11] those with more tracks
@@ -73,18 +74,33 @@ struct TripList {
   int32_t* trips;    // [capacity][2]: frame, packed frame-local i0 | i1 << 8 | i2 << 16
   int32_t* chunks;   // [capacity / kMinChunk + 1][4]
   int capacity, chunk;
+  int pre;           // chunks 0 .. pre-1 belong to waves 0 .. pre-1 of the cuts from the start
 };
 
-// A wave's current chunk; wave-uniform.  cap == 0: no chunk held.
+// A wave's current chunk; wave-uniform.  id >= 0: chunk id is held and its
+// entries [id * chunk, id * chunk + used) are written; kNoChunk: none taken
+// yet; kListFull: the list ran out (stop asking).  Two scalars, so that the
+// loops of the cuts carry little state.
+constexpr int kNoChunk = -1, kListFull = -2;
+
 struct Cursor {
-  int start, cap, used, id;
-  bool full;   // the list ran out: stop asking
+  int id, used;
 };
 
-__device__ inline Cursor cursor_init() { return Cursor{0, 0, 0, -1, false}; }
+// Wave w of the cuts starts with its own chunk w when there is one (so that
+// the waves do not all queue on the bump counter at the start: atomics on
+// one address are serialised); its row is written here.
+__device__ inline Cursor cursor_start(const TripList& T, int w) {
+  if (w >= T.pre) return Cursor{kNoChunk, 0};
+  if (threadIdx.x == 0) {
+    int32_t* row = T.chunks + 4 * w;
+    row[0] = w * T.chunk; row[1] = 0; row[2] = 0; row[3] = 0;
+  }
+  return Cursor{w, 0};
+}
 
 __device__ inline void cursor_close(const Cursor& c, int fitted, const TripList& T) {
-  if (c.cap > 0 && threadIdx.x == 0) {
+  if (c.id >= 0 && threadIdx.x == 0) {
     T.chunks[4 * c.id + 1] = c.used;
     T.chunks[4 * c.id + 2] = fitted;
   }
@@ -92,32 +108,27 @@ __device__ inline void cursor_close(const Cursor& c, int fitted, const TripList&
 
 // All chunks of a launch have the same size, so the k-th grant starts at
 // k * chunk and the granted chunks (those ending within capacity) are rows
-// 0 .. min(counters[7], capacity) / chunk - 1 of the table.
+// 0 .. min(counters[7], capacity) / chunk - 1 of the table (counters[7]
+// starts at pre * chunk: the chunks given out at the start).
 __device__ inline int chunks_granted(const TripList& T, const int32_t* __restrict__ counters) {
   const int handed = counters[7] < T.capacity ? counters[7] : T.capacity;
   return handed / T.chunk;
 }
 
 __device__ inline void cursor_open(Cursor& c, const TripList& T, int32_t* __restrict__ counters) {
-  int start = -1, id = -1;
+  int id = kListFull;
   if (threadIdx.x == 0) {
     const int s0 = atomicAdd(&counters[7], T.chunk);
     if (s0 <= T.capacity - T.chunk) {
       id = s0 / T.chunk;
       int32_t* row = T.chunks + 4 * id;
       row[0] = s0; row[1] = 0; row[2] = 0; row[3] = 0;
-      start = s0;
     } else {
       atomicOr(&counters[2], ST_TRIP_FULL);
     }
   }
-  start = lane_value(start, 0);
-  id = lane_value(id, 0);
-  c.start = start < 0 ? 0 : start;
-  c.cap = start < 0 ? 0 : T.chunk;
+  c.id = lane_value(id, 0);
   c.used = 0;
-  c.id = id;
-  c.full = start < 0;
 }
 
 // Wave ballot of a condition: the condition's lane mask as the compare
@@ -354,14 +365,14 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const unsigned long long bm = ballot(pass);
       const int c = __popcll(bm);
       if (c > 0) {
-        if (cur.used + c > cur.cap && !cur.full) {
+        if (cur.id != kListFull && (cur.id < 0 || cur.used + c > T.chunk)) {
           cursor_close(cur, done, T);
           cursor_open(cur, T, counters);
           done = 0;
         }
-        if (cur.cap > 0) {
+        if (cur.id >= 0) {
           if (pass) {
-            const int slot = cur.start + cur.used + rank_below(bm);
+            const int slot = cur.id * T.chunk + cur.used + rank_below(bm);
             T.trips[2 * slot] = f;
             T.trips[2 * slot + 1] = (int32_t)((uint32_t)j0 | ((uint32_t)j1 << 8) | ((uint32_t)j2 << 16));
           }
@@ -451,16 +462,19 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
   }
   // an overflowing frame is rolled back within the current chunk; entries it
   // left in chunks closed meanwhile are skipped by their frame flag
-  if (ovf && cur.cap > 0) cur.used = cur.id == fid ? fused : 0;
+  if (ovf && cur.id >= 0) cur.used = cur.id == fid ? fused : 0;
   __syncthreads();
   return ovf ? 0 : total;
 }
 
-// End of a wave's cuts: record its last chunk and add its survivors.
+// End of a wave's cuts: record its last chunk and add its survivors to one
+// of kClaimRanges tallies on separate lines (k_scount sums them into
+// counters[0]), so that the waves ending together do not queue on one address.
 __device__ inline void close_list(const Cursor& cur, int done, int selected, const TripList& T,
-                                  int32_t* __restrict__ counters) {
+                                  int32_t* __restrict__ claims) {
   cursor_close(cur, done, T);
-  if (threadIdx.x == 0 && selected > 0) atomicAdd(&counters[0], selected);
+  if (threadIdx.x == 0 && selected > 0)
+    atomicAdd(&claims[(blockIdx.x % kClaimRanges) * kClaimStride + kTallyOffset], selected);
 }
 
 // Runs body(f, regs) for the frames first, next(first), ... (next returns -1
@@ -497,9 +511,9 @@ __global__ void __launch_bounds__(64)
 k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
        const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
        int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
-       int32_t* __restrict__ counters) {
+       int32_t* __restrict__ counters, int32_t* __restrict__ claims) {
   __shared__ CutLds L;
-  Cursor cur = cursor_init();
+  Cursor cur = cursor_start(T, (int)blockIdx.x);
   int done = 0, selected = 0;   // nothing is fitted here
   const int G = gridDim.x;
   frame_pipeline(
@@ -508,7 +522,7 @@ k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __
         selected += cut_frame(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
       },
       lo, X, Y, Z, n_hits);
-  close_list(cur, 0, selected, T, counters);
+  close_list(cur, 0, selected, T, claims);
 }
 
 // ================================================================= k_tracks
@@ -697,10 +711,17 @@ __device__ inline void chunk_slices(const TripList& T, int c, int& nf, int& na) 
 
 // Two passes without atomics, 256 chunks per block: k_scount writes each
 // block's slice totals, k_splace offsets each block by the totals of the
-// blocks before it and writes the tables.
+// blocks before it and writes the tables.  k_scount also sums the cuts'
+// selected-triplet tallies into counters[0].
 __global__ void __launch_bounds__(256)
-k_scount(TripList T, int32_t* __restrict__ blk, const int32_t* __restrict__ counters) {
+k_scount(TripList T, int32_t* __restrict__ blk, int32_t* __restrict__ counters,
+         const int32_t* __restrict__ claims) {
   __shared__ int tmp[512];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int sel = 0;
+    for (int k = 0; k < kClaimRanges; ++k) sel += claims[k * kClaimStride + kTallyOffset];
+    counters[0] = sel;
+  }
   const int nch = chunks_granted(T, counters);
   const int c = blockIdx.x * 256 + (int)threadIdx.x;
   int nf = 0, na = 0;
@@ -797,11 +818,11 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
           TrackOut O, int32_t* __restrict__ counters, int32_t* __restrict__ claims, int claim) {
   __shared__ CutLds L;
   const int lane = threadIdx.x;
-  Cursor cur = cursor_init();
+  Cursor cur = cursor_start(T, (int)blockIdx.x);
   int done = 0, selected = 0;
   auto fit = [&](int k) {   // fit entries [done, done + k) of the current chunk, lane j taking done + j
     const bool active = lane < k;
-    const int e = cur.start + done + lane;
+    const int e = cur.id * T.chunk + done + lane;
     int r = 0, f = 0, i3 = 0;
     float kb = 0.f, c2 = 0.f;
     if (active) {
@@ -856,7 +877,7 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
   if constexpr (kFuse) {
     if (cur.used > done) fit(cur.used - done);
   }
-  close_list(cur, done, selected, T, counters);
+  close_list(cur, done, selected, T, claims);
 }
 
 // Float64 re-evaluation of the entries queued by k_tracks (or the fused
@@ -1515,8 +1536,14 @@ k_align_reduce(const double* __restrict__ partial, int blocks, int np, float* __
   }
 }
 
-__global__ void k_zero(int32_t* __restrict__ p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+// Start of a run: counters cleared except counters[7] = handed0 (the
+// triplet entries of the chunks the cuts' waves start with), and the claim
+// counters and tallies cleared (one block per 4 KiB line group).
+__global__ void __launch_bounds__(256) k_init(int32_t* __restrict__ counters, int handed0,
+                                              int32_t* __restrict__ claims) {
+  const int i = threadIdx.x;
+  if (blockIdx.x == 0 && i < kCounters) counters[i] = i == 7 ? handed0 : 0;
+  for (int j = i; j < kClaimStride; j += 256) claims[blockIdx.x * kClaimStride + j] = 0;
 }
 
 // =============================================================== host side
@@ -1643,6 +1670,7 @@ TripList trip_list(const WsView& W, int capacity, int waves) {
   if (c < kMinChunk) c = kMinChunk;
   if (c > kMaxChunk) c = kMaxChunk;
   T.chunk = (int)c;
+  T.pre = waves < capacity / T.chunk ? waves : capacity / T.chunk;
   return T;
 }
 
@@ -1653,7 +1681,7 @@ void launch_tracks(const mu3e_hits_t& h, const Consts& C, int cus, const WsView&
                    const uint32_t* flags, int32_t* counts, hipStream_t stream, hipEvent_t after_fits) {
   const TrackOut O = track_out(W, counts);
   const int nbk = (int)(((int64_t)T.capacity / T.chunk + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_scount, dim3(nbk), dim3(256), 0, stream, T, W.sblk, W.counters);
+  hipLaunchKernelGGL(k_scount, dim3(nbk), dim3(256), 0, stream, T, W.sblk, W.counters, W.claims);
   hipLaunchKernelGGL(k_splace, dim3(nbk), dim3(256), 0, stream, T, W.S, W.sblk, W.counters);
   // many more waves than fit at once: the slices outnumber them only a few
   // times, and the hardware refills finished waves, which balances better
@@ -1741,13 +1769,13 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
     dbg->chunks = W.chunks; dbg->max_chunks = triplet_capacity / kMinChunk + 1; dbg->chunk_size = T.chunk;
   }
   if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return MU3E_ERR_HIP;
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, W.counters, kCounters);
+  hipLaunchKernelGGL(k_init, dim3(kClaimRanges), dim3(256), 0, stream, W.counters, T.pre * T.chunk, W.claims);
   if (F == 0) {
     for (int k = 1; ev && k < 5; ++k) (void)hipEventRecord(ev[k], stream);
     return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
   }
   hipLaunchKernelGGL(k_cuts, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, F,
-                     hits->n_hits, C, frame_flags, frame_counts, frame_vertex, W.ccnt, T, W.counters);
+                     hits->n_hits, C, frame_flags, frame_counts, frame_vertex, W.ccnt, T, W.counters, W.claims);
   if (ev) (void)hipEventRecord(ev[1], stream);
   launch_tracks(*hits, C, cus, W, T, frame_flags, frame_counts, stream, nullptr);
   if (ev) (void)hipEventRecord(ev[2], stream);
@@ -1874,10 +1902,8 @@ struct mu3e_plan {
 static void plan_launch(const mu3e_plan& pl, hipStream_t s, hipEvent_t* ev) {
   const mu3e_hits_t& h = pl.hits;
   const TrackOut O = track_out(pl.W, pl.counts);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, pl.W.counters, kCounters);
+  hipLaunchKernelGGL(k_init, dim3(kClaimRanges), dim3(256), 0, s, pl.W.counters, pl.T.pre * pl.T.chunk, pl.W.claims);
   if (pl.F == 0) return;
-  if (pl.Fs < pl.F)
-    hipLaunchKernelGGL(k_zero, dim3(kClaimRanges), dim3(256), 0, s, pl.W.claims, kClaimRanges * kClaimStride);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (pl.tuning.fuse_fits)
     hipLaunchKernelGGL(k_batched<true>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, pl.Fs,
