@@ -102,8 +102,9 @@ typedef struct {
 
 /* Optional debug view, filled on return of mu3e_select_frames (host struct
  * holding device pointers into the caller's workspace).  The triplet list
- * is handed out to the waves of the cuts kernel in chunks (one atomic per
- * chunk); a frame's triplets may span chunks.  The track stage stores its
+ * is handed out to the waves of the cuts kernel in chunks (each wave starts
+ * with one of its own, further ones cost one atomic each); a frame's
+ * triplets may span chunks.  The track stage stores its
  * result for every triplet in place (no shared counter).  After the stream
  * is synchronised:
  *   counters[0]  triplets selected in total (true count)
