@@ -213,6 +213,11 @@ def test_batched_small_chunks(lib, fuse):
     assert (fb & 2).sum() > 20   # frames over max_triplets
     tb, kb, kfb, c = b.lists(fs.layer_offsets)
     assert c[2] == 0
+    # counters[0], summed from the waves' tallies: the triplets of frames
+    # that did not overflow, in both forms
+    kept = (fb & 2) == 0
+    for sel in (a, b):
+        assert int(sel.counters()[0]) == int(cb[:, 0][kept].sum()) == len(tb)
     orc = oracle.run(fs, p)
     bad, stats = compare(orc, fb, cb, vb, tb, kb, kfb)
     assert_parity(bad, stats, f"batched small chunks fused={fuse}")
