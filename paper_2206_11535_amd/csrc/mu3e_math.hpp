@@ -259,17 +259,34 @@ __host__ __device__ inline int predict_l3(const Fit<T>& f, float x2, float y2, f
   const T h = m_sqrt(h2 > (T)0 ? h2 : (T)0);
   const T ux = cx / cn, uy = cy / cn;
   const T vx = (T)x2 - cx, vy = (T)y2 - cy;                  // centre -> h2
-  T best = (T)1e30;
-  for (int s = -1; s <= 1; s += 2) {
-    const T qx = a * ux - (T)s * h * uy, qy = a * uy + (T)s * h * ux;
-    const T wx = qx - cx, wy = qy - cy;                      // centre -> crossing
-    // turning angle from h2 to q in the bending sense (clockwise for sgn > 0)
-    T ang = m_atan2(vx * wy - vy * wx, vx * wx + vy * wy);   // counter-clockwise angle
-    if (f.c.sgn > 0) ang = -ang;
-    if (!(ang > (T)0)) ang += (T)(2.0 * kPiD);
-    if (ang < best) { best = ang; px = qx; py = qy; }
+  // Turning angle from h2 to each crossing q in the bending sense (clockwise
+  // for sgn > 0), in (0, 2 pi]: as the pair (cos, sin) * |v||w| = (dot, cross),
+  // cross taken in the bending sense.  The first crossing is chosen by
+  // comparing the pairs (half-turn, then the sign of their cross product),
+  // and only its angle is evaluated.
+  T qx[2], qy[2], dt[2], cr[2];
+  bool upper[2];   // angle in (pi, 2 pi]
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T s = k == 0 ? (T)-1 : (T)1;
+    qx[k] = a * ux - s * h * uy;
+    qy[k] = a * uy + s * h * ux;
+    const T wx = qx[k] - cx, wy = qy[k] - cy;                // centre -> crossing
+    const T c = vx * wy - vy * wx;                           // counter-clockwise sense
+    cr[k] = f.c.sgn > 0 ? -c : c;
+    dt[k] = vx * wx + vy * wy;
+    upper[k] = cr[k] < (T)0 || (cr[k] == (T)0 && !(dt[k] < (T)0));
   }
-  pz = (T)z2 + best * f.c.z2 / f.phi2;
+  // crossing 1 comes strictly first: an earlier half-turn, or the same one
+  // and a counter-clockwise turn from crossing 1 to crossing 0 (ties keep 0)
+  const bool second = (!upper[1] && upper[0]) ||
+                      (upper[1] == upper[0] && dt[0] * cr[1] - cr[0] * dt[1] < (T)0);
+  const int k = second ? 1 : 0;
+  T ang = m_atan2(second ? cr[1] : cr[0], second ? dt[1] : dt[0]);
+  if (!(ang > (T)0)) ang += (T)(2.0 * kPiD);
+  px = qx[k];
+  py = qy[k];
+  pz = (T)z2 + ang * f.c.z2 / f.phi2;
   return 1;
 }
 

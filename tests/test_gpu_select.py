@@ -223,6 +223,34 @@ def test_batched_small_chunks(lib, fuse):
     assert_parity(bad, stats, f"batched small chunks fused={fuse}")
 
 
+@pytest.mark.parametrize("cap", [40, 3000])
+def test_triplet_list_full(lib, cap):
+    """A triplet list too small for the batch (below one chunk, and a few
+    chunks): both forms report it in the status word (bit 1) instead of
+    writing past it, and the per-frame triplet counts stay exact."""
+    import torch
+    fs = synth.generate(2, n_frames=2000)
+    p = default_params()
+    dh = lib.to_device(fs)
+    ref = lib.select_frames(dh, p)
+    print(f"case: triplet list of {cap} entries", flush=True)
+    a = lib.select_frames(dh, p, triplet_capacity=cap)
+    b = lib.BatchedSelector(dh, p, triplet_capacity=cap, waves_per_cu=4, frames_per_claim=2, steal_percent=25)
+    b.run()
+    torch.cuda.synchronize()
+    _, cr, _ = ref.result()
+    assert ref.counters()[2] == 0
+    for sel in (a, b):
+        c = sel.counters()
+        assert c[2] & 1, c
+        _, cs, _ = sel.result()
+        assert np.array_equal(cs[:, 0], cr[:, 0])
+    # the plan runs again, still reporting the full list
+    b.run()
+    torch.cuda.synchronize()
+    assert b.counters()[2] & 1
+
+
 def test_fit_triplets(lib):
     import torch
     fs = synth.generate(2, n_frames=3000)
