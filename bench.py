@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import gc
 import hashlib
 import json
 import os
@@ -50,8 +51,8 @@ FLOPS_PAIR01, FLOPS_PAIR12, FLOPS_JOIN, FLOPS_RTC = 4, 6, 3, 24
 # "<hash of the kernel sources>|<kernel>" of the build it was measured on
 # (null once the source changes).
 TRAFFIC = {
-    # profiles/nominal_hbm_traffic.md: 88.68 MB read + 23.30 MB written per launch
-    "04e8e485ee8be4ef|k_batched": 111976347,
+    # profiles/nominal_hbm_traffic.md: 88.67 MB read + 23.23 MB written per launch
+    "09e507f97ba27fe3|k_batched": 111897166,
 }
 
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X float32 vector (published)
@@ -155,6 +156,7 @@ def time_inflight(plans, streams, hip, steps, warmup):
             raise RuntimeError(f"candidate lists overflowed the workspace: {c}")
     ev = [hip.events(2) for _ in range(steps)]
     torch.cuda.synchronize()
+    gc.disable()   # no collector pause while the host feeds the streams
     t0 = time.perf_counter()
     for k in range(steps):
         st = streams[k % n]
@@ -163,6 +165,7 @@ def time_inflight(plans, streams, hip, steps, warmup):
         hip.record(ev[k][1], st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     lat = float(np.mean([hip.elapsed(e[0], e[1]) for e in ev]))
     return wall / steps * 1e3, lat, wall
 
@@ -238,8 +241,8 @@ def same_outputs(a, b) -> bool:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=None, help="prefix of the workload (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed", action="store_true", help="also the mixed-rate 1,000,000-frame batch")
