@@ -64,10 +64,10 @@ enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
 __device__ inline int lane_value(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
 
 // ----------------------------------------------------------- triplet list
-// Selected triplets are appended to chunks of one list: a wave takes a chunk
-// from a bump counter (one atomic per chunk) and fills it with ballot
-// compaction; when a wave's survivors do not fit, it closes the chunk and
-// takes the next, so a frame may span chunks.  Chunk table row c holds
+// Selected triplets are appended to chunks of one list: each wave of the
+// cuts starts with a chunk of its own, fills it with ballot compaction, and
+// when its survivors do not fit closes it and takes the next from a bump
+// counter (one atomic per further chunk), so a frame may span chunks.  Chunk table row c holds
 // [start, count, fitted, 0]; entries [fitted, count) of a chunk are fitted by
 // k_tracks (the batched form fits the rest itself).
 struct TripList {
@@ -254,12 +254,13 @@ __device__ inline bool cos_cut_wave(bool act, float x0, float y0, float x1, floa
 
 // =================================================================== k_cuts
 constexpr int kJoinQueue = 2 * 64;   // combinations passing Delta lambda awaiting r_tc (< 2 waves)
+constexpr uint32_t kDlAmbiguous = 1u << 24;   // queued combination whose Delta lambda float32 cannot decide
 
 struct CutLds {
   float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
   unsigned long long sm01[2 * kMaxLayerHits];
   uint32_t spend[2 * kWave];
-  uint32_t sjoin[kJoinQueue];   // packed i1 | i2 << 8 | i0 << 16
+  uint32_t sjoin[kJoinQueue];   // packed i1 | i2 << 8 | i0 << 16, kDlAmbiguous
 };
 
 // ------------------------------------------------------------ frame loads
@@ -353,7 +354,8 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
         atomicOr(&L.sm01[2 * i1 + (i0 >> 6)], 1ull << (i0 & 63));
     }
     __syncthreads();
-    // r_tc test of the first m (<= kWave) queued combinations, one per lane;
+    // r_tc test of the first m (<= kWave) queued combinations, one per lane
+    // (with the float64 Delta lambda decision of those marked ambiguous);
     // survivors are ballot-compacted into the wave's chunks of the list.
     auto test = [&](int m) {
       const bool act = lane < m;
@@ -364,8 +366,13 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
       const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
       bool rpass = vr.pass;
-      if (ballot(act && vr.amb) != 0ull) {   // rare: float64 where float32 cannot decide
-        if (act && vr.amb) rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
+      const bool damb = act && (c3 & kDlAmbiguous);
+      if (ballot(damb || (act && vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
+        if (damb && !dl_refine(L.sz[j0], L.sz[kMaxLayerHits + j1], L.sz[2 * kMaxLayerHits + j2], C.R[0], C.R[1],
+                               C.R[2], C.dl_lo, C.dl_hi))
+          rpass = false;
+        else if (act && vr.amb)
+          rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
       }
       const bool pass = act && rpass;
       const unsigned long long bm = ballot(pass);
@@ -412,12 +419,11 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
         w1 = in0 ? w1 : rest;
         const float z0 = L.sz[i0];
         const Verdict vd = dl_test(z0, z1, t12, C);
-        bool pass = has && vd.pass;
-        if (ballot(has && vd.amb) != 0ull) {   // rare: float64 where float32 cannot decide
-          if (has && vd.amb) pass = dl_refine(z0, z1, z2, C.R[0], C.R[1], C.R[2], C.dl_lo, C.dl_hi);
-        }
+        // ambiguous combinations are queued too, marked; the r_tc stage
+        // decides them in float64 (rare), so the rounds carry no branch
+        const bool pass = has && (vd.pass || vd.amb);
         const unsigned long long bm = ballot(pass);
-        if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16);
+        if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16) | (vd.amb ? kDlAmbiguous : 0u);
         nq += __popcll(bm);
         if (nq >= kWave) {
           __syncthreads();
