@@ -38,7 +38,25 @@ struct Consts {
   float rtc_lo2, rtc_hi2;    // squared |r_tc| edges
 };
 
-__host__ __device__ inline float m_sqrt(float x) { return sqrtf(x); }
+// float32 quotient and square root on the device straight from the hardware
+// reciprocal and root (about 1 ulp each, no rescaling of denormal or
+// near-overflow operands: the fit's magnitudes stay far from both ends); the
+// float64 overloads are exact operations.
+__host__ __device__ inline float m_div(float a, float b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return a * __builtin_amdgcn_rcpf(b);
+#else
+  return a / b;
+#endif
+}
+__host__ __device__ inline double m_div(double a, double b) { return a / b; }
+__host__ __device__ inline float m_sqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
 __host__ __device__ inline double m_sqrt(double x) { return sqrt(x); }
 __host__ __device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
 __host__ __device__ inline double m_atan2(double y, double x) { return atan2_full(y, x); }
@@ -82,8 +100,8 @@ __host__ __device__ inline Circle<T> circle3(double x0, double y0, double z0, do
   c.sgn = c.cross > 0.0 ? 1 : -1;
   // |r_tc| = sqrt(aa bb ee) / (2 |cross|); centre relative to h1
   const T taa = (T)aa, tbb = (T)bb, tee = (T)ee, tcr = (T)c.cross;
-  c.rho = m_sqrt(taa) * m_sqrt(tbb) * m_sqrt(tee) / ((T)2 * m_abs(tcr));
-  const T inv = (T)0.5 / tcr;
+  c.rho = m_div(m_sqrt(taa) * m_sqrt(tbb) * m_sqrt(tee), (T)2 * m_abs(tcr));
+  const T inv = m_div((T)0.5, tcr);
   c.cx = (T)x1 + ((T)by * taa - (T)ay * tbb) * inv;
   c.cy = (T)y1 + ((T)ax * tbb - (T)bx * taa) * inv;
   c.d1 = m_sqrt(taa);
@@ -97,8 +115,8 @@ __host__ __device__ inline Circle<T> circle3(double x0, double y0, double z0, do
   const double n1 = fabs(bb + ee - aa), n2 = fabs(aa + ee - bb);
   if (sizeof(T) == 4) {   // float32 quotients of the exact float64 terms
     const float a2 = (float)(2.0 * acr);
-    c.cot1 = (T)((float)n1 / a2);
-    c.cot2 = (T)((float)n2 / a2);
+    c.cot1 = (T)m_div((float)n1, a2);
+    c.cot2 = (T)m_div((float)n2, a2);
   } else {
     c.cot1 = (T)(n1 / (2.0 * acr));
     c.cot2 = (T)(n2 / (2.0 * acr));
@@ -181,12 +199,13 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
     const T arc = rho * phi[k];                              // transverse arc length
     const T len = m_sqrt(arc * arc + zk[k] * zk[k]);
     th[k] = m_atan2(arc, zk[k]);                             // output only
-    sth[k] = arc / len;                                      // sin(theta_k)
-    cth[k] = zk[k] / len;                                    // cos(theta_k)
-    Rk[k] = rho / sth[k];
-    const T D = rho * rho * cot + (T)2 * zk[k] * zk[k] / (phi[k] * phi[k] * phi[k]);
-    al[k] = -(T)2 * Rk[k] / D;
-    be[k] = zk[k] * rho * rho * phicot_minus_2(phi[k], cot) / (D * Rk[k] * Rk[k] * phi[k] * phi[k] * sth[k]);
+    const T ilen = m_div((T)1, len);
+    sth[k] = arc * ilen;                                     // sin(theta_k)
+    cth[k] = zk[k] * ilen;                                   // cos(theta_k)
+    Rk[k] = m_div(rho, sth[k]);
+    const T D = rho * rho * cot + m_div((T)2 * zk[k] * zk[k], phi[k] * phi[k] * phi[k]);
+    al[k] = m_div(-(T)2 * Rk[k], D);
+    be[k] = m_div(zk[k] * rho * rho * phicot_minus_2(phi[k], cot), D * Rk[k] * Rk[k] * phi[k] * phi[k] * sth[k]);
   }
   const T Rbar = (T)0.5 * (Rk[0] + Rk[1]);
   // theta_2 - theta_1 = atan2(rho K, rho^2 Phi1 Phi2 + z1 z2) and
@@ -204,21 +223,22 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
   // sin th1 + sin th2 = 2 sin(mean) cos(half difference), and the half
   // difference's cosine is sqrt((1 + cos(th1 - th2)) / 2), both well
   // conditioned as th1 ~ th2 (no arctangent or sine evaluated)
-  const T sn = (sth[0] + sth[1]) / m_sqrt((T)2 * ((T)1 + cth[0] * cth[1] + sth[0] * sth[1]));
+  const T sn = m_div(sth[0] + sth[1], m_sqrt((T)2 * ((T)1 + cth[0] * cth[1] + sth[0] * sth[1])));
   const T s2 = sn * sn;
   const T p = (T)kCLight * (T)C.b * Rbar;
-  const T X = (T)C.xx0 / sn;
-  const T sms = (T)13.6 / p * m_sqrt(X) * ((T)1 + (T)0.038 * m_log(X));
+  const T X = m_div((T)C.xx0, sn);
+  const T sms = m_div((T)13.6, p) * m_sqrt(X) * ((T)1 + (T)0.038 * m_log(X));
   const T den = s2 * bphi * bphi + bth * bth;
   if (!(den > (T)0) || !(sms > (T)0)) return f;
   const T num = phi0 * bth - th0 * bphi;
   const T sms2 = sms * sms;
-  f.rstar = Rbar - (s2 * phi0 * bphi + th0 * bth) / den;
-  f.s2r = sms2 / den;
-  f.chi2 = s2 * num * num / (den * sms2);
-  f.kappa = (T)f.c.sgn / f.rstar;
+  const T iden = m_div((T)1, den);
+  f.rstar = Rbar - (s2 * phi0 * bphi + th0 * bth) * iden;
+  f.s2r = sms2 * iden;
+  f.chi2 = m_div(s2 * num * num * iden, sms2);
+  f.kappa = m_div((T)f.c.sgn, f.rstar);
   const T r2 = f.rstar * f.rstar;
-  f.s2kappa = f.s2r / (r2 * r2);
+  f.s2kappa = m_div(f.s2r, r2 * r2);
   f.th1 = th[0];
   f.th2 = th[1];
   f.sth1 = sth[0];
@@ -233,11 +253,11 @@ __host__ __device__ inline Fit<T> fit_triplet(double x0, double y0, double z0, d
 // triplets' quadratic chi2 evaluated at R = 1/|kbar|.
 template <class T>
 __host__ __device__ inline void combine(const Fit<T>& a, const Fit<T>& b, T& kbar, T& chi2) {
-  const T wa = (T)1 / a.s2kappa, wb = (T)1 / b.s2kappa;
-  kbar = (a.kappa * wa + b.kappa * wb) / (wa + wb);
-  const T R = (T)1 / m_abs(kbar);
+  const T wa = m_div((T)1, a.s2kappa), wb = m_div((T)1, b.s2kappa);
+  kbar = m_div(a.kappa * wa + b.kappa * wb, wa + wb);
+  const T R = m_div((T)1, m_abs(kbar));
   const T da = R - a.rstar, db = R - b.rstar;
-  chi2 = a.chi2 + da * da / a.s2r + b.chi2 + db * db / b.s2r;
+  chi2 = a.chi2 + m_div(da * da, a.s2r) + b.chi2 + m_div(db * db, b.s2r);
 }
 
 // ---------------------------------------------------------- layer-3 point
@@ -254,10 +274,11 @@ __host__ __device__ inline int predict_l3(const Fit<T>& f, float x2, float y2, f
   const T outer = rho + R3, inner = m_abs(rho - R3);
   if (near) *near = m_abs(cn - outer) <= tol * outer || m_abs(cn - inner) <= tol * outer;
   if (!(cn > (T)0) || cn > outer || cn < inner) return 0;
-  const T a = (R3 * R3 - rho * rho + cn * cn) / ((T)2 * cn);
+  const T icn = m_div((T)1, cn);
+  const T a = (R3 * R3 - rho * rho + cn * cn) * (T)0.5 * icn;
   T h2 = R3 * R3 - a * a;
   const T h = m_sqrt(h2 > (T)0 ? h2 : (T)0);
-  const T ux = cx / cn, uy = cy / cn;
+  const T ux = cx * icn, uy = cy * icn;
   const T vx = (T)x2 - cx, vy = (T)y2 - cy;                  // centre -> h2
   // Turning angle from h2 to each crossing q in the bending sense (clockwise
   // for sgn > 0), in (0, 2 pi]: as the pair (cos, sin) * |v||w| = (dot, cross),
@@ -286,14 +307,14 @@ __host__ __device__ inline int predict_l3(const Fit<T>& f, float x2, float y2, f
   if (!(ang > (T)0)) ang += (T)(2.0 * kPiD);
   px = qx[k];
   py = qy[k];
-  pz = (T)z2 + ang * f.c.z2 / f.phi2;
+  pz = (T)z2 + m_div(ang * f.c.z2, f.phi2);
   return 1;
 }
 
 // Highland width of the projected scattering angle (beta = 1).
 template <class T>
 __host__ __device__ inline T highland(T p, T x) {
-  return (T)13.6 / p * m_sqrt(x) * ((T)1 + (T)0.038 * m_log(x));
+  return m_div((T)13.6, p) * m_sqrt(x) * ((T)1 + (T)0.038 * m_log(x));
 }
 
 }  // namespace mu3e
