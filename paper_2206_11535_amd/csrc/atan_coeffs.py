@@ -6,6 +6,9 @@ residual the relative error of atan) of (atan(sqrt s) - sqrt s) / s^(3/2) on
 Chebyshev nodes of [0, tan(pi/8)^2], in 60-digit arithmetic (mpmath).  The
 fit's relative error of atan is below 4e-17 on the interval.
 
+The float32 version (atan2f_full) uses the same fit with five terms
+(fit(n=5), relative error below 1e-9).
+
 Run: python atan_coeffs.py  (prints the coefficients and the error bound)
 """
 import mpmath as mp

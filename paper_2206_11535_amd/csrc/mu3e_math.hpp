@@ -58,13 +58,19 @@ __host__ __device__ inline float m_sqrt(float x) {
 #endif
 }
 __host__ __device__ inline double m_sqrt(double x) { return sqrt(x); }
-__host__ __device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
+__host__ __device__ inline float m_atan2(float y, float x) { return atan2f_full(y, x); }
 __host__ __device__ inline double m_atan2(double y, double x) { return atan2_full(y, x); }
 __host__ __device__ inline float m_sin(float x) { return sinf(x); }
 __host__ __device__ inline double m_sin(double x) { return sin(x); }
 __host__ __device__ inline float m_cos(float x) { return cosf(x); }
 __host__ __device__ inline double m_cos(double x) { return cos(x); }
-__host__ __device__ inline float m_log(float x) { return logf(x); }
+__host__ __device__ inline float m_log(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_logf(x) * 0.693147180559945f;   // hardware log2 (about 1 ulp)
+#else
+  return logf(x);
+#endif
+}
 __host__ __device__ inline double m_log(double x) { return log(x); }
 __host__ __device__ inline float m_abs(float x) { return fabsf(x); }
 __host__ __device__ inline double m_abs(double x) { return fabs(x); }

@@ -52,7 +52,27 @@ int main() {
     const int64_t d = ulps(mu3e::atan2_full(p[0], p[1]), atan2(p[0], p[1]));
     if (d > edge) edge = d;
   }
-  printf("%lld %lld %lld\n", (long long)worst_q1, (long long)worst_full, (long long)edge);
+  // the float32 version against the C library's atan2f
+  int64_t worst_f = 0;
+  for (int k = 0; k < 2000000; ++k) {
+    float y = (float)drand48(), x = (float)drand48();
+    if (k % 4 == 1) y *= 1e-6f;
+    if (k % 4 == 2) x *= 1e-6f;
+    if (k % 4 == 3) {
+      const int e = (int)(drand48() * 100) - 50;
+      y = ldexpf(y, e + (int)(drand48() * 20) - 10);
+      x = ldexpf(x, e);
+    }
+    if (k & 1) y = -y;
+    if (k & 2) x = -x;
+    const float a = mu3e::atan2f_full(y, x), b = atan2f(y, x);
+    int32_t ia, ib;
+    memcpy(&ia, &a, 4);
+    memcpy(&ib, &b, 4);
+    const int64_t d = a == b ? 0 : (signbit(a) != signbit(b) ? (1LL << 40) : llabs((int64_t)ia - (int64_t)ib));
+    if (d > worst_f) worst_f = d;
+  }
+  printf("%lld %lld %lld %lld\n", (long long)worst_q1, (long long)worst_full, (long long)edge, (long long)worst_f);
   return 0;
 }
 """
@@ -64,7 +84,8 @@ def test_atan2_against_libm(tmp_path):
     src.write_text(PROGRAM)
     exe = tmp_path / "t"
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", CSRC, "-o", str(exe), str(src), "-lm"])
-    worst_q1, worst_full, edge = map(int, subprocess.check_output([str(exe)], text=True).split())
+    worst_q1, worst_full, edge, worst_f = map(int, subprocess.check_output([str(exe)], text=True).split())
+    assert worst_f <= 4, worst_f
     assert worst_q1 <= 2, worst_q1
     assert worst_full <= 2, worst_full
     assert edge <= 1, edge
