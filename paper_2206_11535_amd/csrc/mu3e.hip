@@ -343,7 +343,10 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
   if (n0 > 0 && n2 > 0) {
     // ---- Phi01 over all (i0, i1) pairs
     const int n01 = n0 * n1;
-    const float r0 = 1.0f / (float)n0;
+    // hardware reciprocal (about 1 ulp): (p + 0.5) / n0 stays at least
+    // 0.5 / n0 >= 1/256 from an integer, far above its rounding error, so the
+    // truncation below is exact
+    const float r0 = __builtin_amdgcn_rcpf((float)n0);
     for (int base = 0; base < n01; base += kWave) {
       const int p = base + lane;
       const bool act = p < n01;
@@ -440,7 +443,7 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
     int npend = 0;
     const int n12 = n1 * n2;
-    const float r2 = 1.0f / (float)n2;
+    const float r2 = __builtin_amdgcn_rcpf((float)n2);
     for (int base = 0; base < n12; base += kWave) {
       const int p = base + lane;
       const bool inr = p < n12;
