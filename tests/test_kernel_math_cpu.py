@@ -89,3 +89,21 @@ def test_atan2_against_libm(tmp_path):
     assert worst_q1 <= 2, worst_q1
     assert worst_full <= 2, worst_full
     assert edge <= 1, edge
+
+
+def test_pair_index_split_with_approximate_reciprocal():
+    """The cuts split a flat pair index p < n * m into (p // n, p % n) as the
+    float32 truncation of (p + 0.5) * r with r the hardware reciprocal of n
+    (about 1 ulp): the split stays exact for every n <= 128 and p < 128 n
+    with r off by up to 2 ulp either way (float32 arithmetic emulated)."""
+    import numpy as np
+    for n in range(1, 129):
+        p = np.arange(n * 128, dtype=np.int64)
+        pf = p.astype(np.float32) + np.float32(0.5)
+        r = np.float32(1.0) / np.float32(n)
+        for step in (-2, -1, 0, 1, 2):
+            rr = r
+            for _ in range(abs(step)):
+                rr = np.nextafter(rr, np.float32(np.inf if step > 0 else -np.inf), dtype=np.float32)
+            q = (pf * rr).astype(np.float32).astype(np.int32)
+            assert np.array_equal(q, p // n), (n, step)
