@@ -254,13 +254,14 @@ __device__ inline bool cos_cut_wave(bool act, float x0, float y0, float x1, floa
 
 // =================================================================== k_cuts
 constexpr int kJoinQueue = 2 * 64;   // combinations passing Delta lambda awaiting r_tc (< 2 waves)
-constexpr uint32_t kDlAmbiguous = 1u << 24;   // queued combination whose Delta lambda float32 cannot decide
+constexpr uint32_t kDlAmbiguous = 1u << 24;     // queued combination whose Delta lambda float32 cannot decide
+constexpr uint32_t kPhi12Ambiguous = 1u << 25;  // queued pair / combination whose cos Phi12 float32 cannot decide
 
 struct CutLds {
   float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
   unsigned long long sm01[2 * kMaxLayerHits];
   uint32_t spend[2 * kWave];
-  uint32_t sjoin[kJoinQueue];   // packed i1 | i2 << 8 | i0 << 16, kDlAmbiguous
+  uint32_t sjoin[kJoinQueue];   // packed i1 | i2 << 8 | i0 << 16, kDlAmbiguous, kPhi12Ambiguous
 };
 
 // ------------------------------------------------------------ frame loads
@@ -358,7 +359,8 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     }
     __syncthreads();
     // r_tc test of the first m (<= kWave) queued combinations, one per lane
-    // (with the float64 Delta lambda decision of those marked ambiguous);
+    // (with the float64 Phi12 and Delta lambda decisions of those marked
+    // ambiguous);
     // survivors are ballot-compacted into the wave's chunks of the list.
     auto test = [&](int m) {
       const bool act = lane < m;
@@ -369,10 +371,11 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
       const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
       bool rpass = vr.pass;
-      const bool damb = act && (c3 & kDlAmbiguous);
-      if (ballot(damb || (act && vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
-        if (damb && !dl_refine(L.sz[j0], L.sz[kMaxLayerHits + j1], L.sz[2 * kMaxLayerHits + j2], C.R[0], C.R[1],
-                               C.R[2], C.dl_lo, C.dl_hi))
+      const bool damb = act && (c3 & kDlAmbiguous), pamb = act && (c3 & kPhi12Ambiguous);
+      if (ballot(damb || pamb || (act && vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
+        if ((pamb && !cos_refine(x1, y1, x2, y2, C.c12_lo, C.c12_hi, C.R[1], C.R[2])) ||
+            (damb && !dl_refine(L.sz[j0], L.sz[kMaxLayerHits + j1], L.sz[2 * kMaxLayerHits + j2], C.R[0], C.R[1],
+                                C.R[2], C.dl_lo, C.dl_hi)))
           rpass = false;
         else if (act && vr.amb)
           rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
@@ -450,11 +453,14 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       const int i1 = inr ? (int)(((float)p + 0.5f) * r2) : 0;
       const int i2 = inr ? p - i1 * n2 : 0;
       const bool act = inr && (L.sm01[2 * i1] | L.sm01[2 * i1 + 1]) != 0ull;
-      const bool pass = cos_cut_wave(act, L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1],
-                                     L.sx[2 * kMaxLayerHits + i2], L.sy[2 * kMaxLayerHits + i2], C.invRR12,
-                                     C.c12_lo, C.c12_hi, C.R[1], C.R[2]);
+      // pairs float32 cannot decide are queued too, marked, and decided in
+      // float64 by the r_t,c stage for the combinations that reach it
+      const Verdict v = cos_test(L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], L.sx[2 * kMaxLayerHits + i2],
+                                 L.sy[2 * kMaxLayerHits + i2], C.invRR12, C.c12_lo, C.c12_hi);
+      const bool pass = act && (v.pass || v.amb);
       const unsigned long long bm = ballot(pass);
-      if (pass) L.spend[npend + rank_below(bm)] = (uint32_t)i1 | ((uint32_t)i2 << 8);
+      if (pass)
+        L.spend[npend + rank_below(bm)] = (uint32_t)i1 | ((uint32_t)i2 << 8) | (v.amb ? kPhi12Ambiguous : 0u);
       npend += __popcll(bm);
       if (npend >= kWave) {
         __syncthreads();
