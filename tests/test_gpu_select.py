@@ -223,6 +223,39 @@ def test_batched_small_chunks(lib, fuse):
     assert_parity(bad, stats, f"batched small chunks fused={fuse}")
 
 
+def test_edges_on_candidates(lib):
+    """Cut windows whose edges sit on the float32-rounded value of a true
+    triplet's Delta lambda, cos Phi01, cos Phi12 or |r_tc|: float32 cannot
+    decide those candidates, so every float64 decision of the cuts runs
+    (the Phi12 and Delta lambda ones deferred to the r_tc stage).  A
+    float32-rounded edge lies ~1e-8 (relative) from the float64 value, so
+    the oracle, run with an ambiguity band of 1e-12 instead of 1e-5, decides
+    them, and both forms must agree with it."""
+    import torch
+    fs = synth.generate(2, n_frames=400, salt=21)
+    p = default_params()
+    tt, _, _ = synth.true_triplets(fs)
+    h = np.stack([np.stack([fs.x[tt[:, k]], fs.y[tt[:, k]], fs.z[tt[:, k]]], 1) for k in range(3)], 1)
+    q, dec = oracle.cut_quantities(h.astype(np.float64), p)
+    q = q[dec == 1]
+    assert len(q) > 100
+
+    def at(v, frac):   # the float32 value of the element at this rank
+        return float(np.float32(np.sort(v)[int(frac * (len(v) - 1))]))
+
+    dl, c01, c12, rt = q[:, 0], q[:, 1], q[:, 2], np.abs(q[:, 3])
+    pe = dict(p, amb=1e-12, dlambda=(at(dl[dl < 0], 0.3), at(dl[dl > 0], 0.7)),
+              cosphi01=(at(c01, 0.3), 2.0), cosphi12=(at(c12, 0.3), 2.0), rtc_abs=(at(rt, 0.2), at(rt, 0.8)))
+    orc, flags, counts = check(lib, fs, pe, "edges on candidates, plain")
+    assert int((orc.namb).sum()) == 0
+    dh = lib.to_device(fs)
+    b = lib.BatchedSelector(dh, pe, waves_per_cu=4, frames_per_claim=2, steal_percent=25)
+    b.run()
+    torch.cuda.synchronize()
+    fb, cb, vb = b.result()
+    assert np.array_equal(fb, flags) and np.array_equal(cb, counts)
+
+
 @pytest.mark.parametrize("cap", [40, 3000])
 def test_triplet_list_full(lib, cap):
     """A triplet list too small for the batch (below one chunk, and a few
