@@ -1548,13 +1548,30 @@ k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const floa
   for (int j = threadIdx.x; j < np; j += blockDim.x) partial[(size_t)blockIdx.x * np + j] = acc[j];
 }
 
+// Column sums of the per-block rows of partial ([blocks][np] float64):
+// block x takes 64 columns, each of its four waves every fourth row with
+// eight independent sums per lane (so that eight loads are in flight), the
+// eight and then the four waves' sums added in a fixed order (the result is
+// deterministic).
 __global__ void __launch_bounds__(256)
 k_align_reduce(const double* __restrict__ partial, int blocks, int np, float* __restrict__ grad) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < np; j += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * np + j];
-    grad[j] = (float)s;
+  __shared__ double part[4][kWave];
+  const int l = (int)threadIdx.x % kWave, w = (int)threadIdx.x / kWave;
+  const int j = (int)blockIdx.x * kWave + l;
+  double s = 0.0;
+  if (j < np) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int b = w;
+    for (; b + 28 < blocks; b += 32) {   // rows b, b + 4, ..., b + 28
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] += partial[(size_t)(b + 4 * k) * np + j];
+    }
+    for (; b < blocks; b += 4) a[0] += partial[(size_t)b * np + j];
+    s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
+  part[w][l] = s;
+  __syncthreads();
+  if (w == 0 && j < np) grad[j] = (float)((part[0][l] + part[1][l]) + (part[2][l] + part[3][l]));
 }
 
 // Start of a run: counters cleared except counters[7] = handed0 (the
@@ -1896,7 +1913,7 @@ mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, in
   hipLaunchKernelGGL(k_align_bwd, dim3(kAlignBlocks), dim3(256), (size_t)np * sizeof(double), stream, hits->x, hits->y,
                      hits->z, hits->sensor,
                      hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial);
-  hipLaunchKernelGGL(k_align_reduce, dim3((np + 255) / 256), dim3(256), 0, stream, partial, kAlignBlocks, np,
+  hipLaunchKernelGGL(k_align_reduce, dim3((np + kWave - 1) / kWave), dim3(256), 0, stream, partial, kAlignBlocks, np,
                      grad_theta);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
