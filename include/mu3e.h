@@ -222,7 +222,9 @@ mu3e_status mu3e_vertex(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
  * follow in the same graph.  Outputs are identical to mu3e_select_frames.
  * The plan binds the hit, output and workspace buffers given here: refill
  * them and call mu3e_plan_run again.  Runs of one plan (or of plans sharing
- * a workspace) must not overlap. */
+ * a workspace) must not overlap; plans with their own buffers may run at the
+ * same time on different streams (several batches in flight, each batch's
+ * latency-bound stages overlapping another's cuts). */
 typedef struct mu3e_plan mu3e_plan_t;
 
 typedef struct {
