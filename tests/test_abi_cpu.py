@@ -97,3 +97,18 @@ def test_host_validation(L):
     assert plan.value is None
     # timed plan run without a plan or events
     assert L.mu3e_plan_run_timed(None, None, None) == -1
+
+
+def test_binding_fails_loudly_without_library():
+    """The binding has no CPU fallback: with the shared library missing,
+    loading it raises instead of computing anything elsewhere."""
+    import subprocess
+    import sys
+    code = ("from paper_2206_11535_amd import lib\n"
+            "try:\n"
+            "    lib.load('/nonexistent/libmu3e.so')\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0 and out.stdout.startswith("raised"), out.stdout + out.stderr
