@@ -363,6 +363,14 @@ def sampled_parity(fs, p, sel, what, n_pick=2000, seed=7):
     assert c[2] == 0
     rng = np.random.default_rng(seed)
     pick = np.sort(rng.choice(fs.n_frames, n_pick, replace=False))
+    # group the lists by frame once (a stable sort keeps each frame's rows in
+    # list order), so each picked frame's rows are one contiguous slice
+    ot = np.argsort(trips[:, 0], kind="stable")
+    trips = trips[ot]
+    ok_ = np.argsort(tracks[:, 0], kind="stable")
+    tracks, kf = tracks[ok_], kf[ok_]
+    t_lo, t_hi = np.searchsorted(trips[:, 0], pick, "left"), np.searchsorted(trips[:, 0], pick, "right")
+    k_lo, k_hi = np.searchsorted(tracks[:, 0], pick, "left"), np.searchsorted(tracks[:, 0], pick, "right")
     # oracle on the picked frames, one sub-batch per frame (hit indices rebased)
     sub_trips, sub_tracks, sub_kf = [], [], []
     orcs = []
@@ -370,13 +378,11 @@ def sampled_parity(fs, p, sel, what, n_pick=2000, seed=7):
         sub = fs.subset(int(f), int(f) + 1)
         orcs.append(oracle.run(sub, p))
         base = fs.layer_offsets[4 * f]
-        m = trips[:, 0] == f
-        t = trips[m].copy(); t[:, 0] = i; t[:, 1:] -= base
+        t = trips[t_lo[i]:t_hi[i]].copy(); t[:, 0] = i; t[:, 1:] -= base
         sub_trips.append(t)
-        m = tracks[:, 0] == f
-        k = tracks[m].copy(); k[:, 0] = i; k[:, 1:] -= base
+        k = tracks[k_lo[i]:k_hi[i]].copy(); k[:, 0] = i; k[:, 1:] -= base
         sub_tracks.append(k)
-        sub_kf.append(kf[m])
+        sub_kf.append(kf[k_lo[i]:k_hi[i]])
     # merge the per-frame oracle results into one result over len(pick) frames
     orc = oracle.OracleResult(
         np.concatenate([o.flags for o in orcs]), np.concatenate([o.amb for o in orcs]),
