@@ -99,6 +99,64 @@ def test_layer_hit_overflow(lib):
     assert (flags & 32).sum() > 10
 
 
+# hits per layer (0..3) of the limit frames: the largest count a layer may
+# hold (128: the frame's staged hits fill the LDS slots, 16,384 pairs per
+# layer pair), one less, and one more on each kind of layer
+LIMIT_FILL = [(128, 128, 128, 128), (128, 128, 128, 40), (129, 20, 20, 20), (20, 20, 20, 129),
+              (30, 128, 30, 30), (128, 30, 128, 30), (127, 128, 127, 128), (128, 129, 128, 128)]
+
+
+def limit_frames(seed=5):
+    """High-rate Michel frames with each layer cut or padded with noise hits
+    (pixel centres on the layer's cylinder) to the counts of LIMIT_FILL,
+    the hits of a layer in random order."""
+    from helpers import Frames
+    base = synth.generate(dataclasses.replace(synth.CONFIGS[1], lam=22.0, noise_per_layer=0),
+                          n_frames=len(LIMIT_FILL), salt=21)
+    rng = np.random.default_rng(seed)
+    frames = []
+    for f, want in enumerate(LIMIT_FILL):
+        fr = []
+        for l in range(4):
+            a, b = base.layer_offsets[4 * f + l], base.layer_offsets[4 * f + l + 1]
+            pts = np.stack([base.x[a:b], base.y[a:b], base.z[a:b]], 1)[:want[l]].astype(float)
+            k = want[l] - len(pts)
+            phi = rng.uniform(-np.pi, np.pi, k)
+            zt = rng.uniform(-1.0, 1.0, k) * synth.Z_HALF[l]
+            x, y, z = synth.quantise(phi, zt, synth.R_LAYER[l])
+            z = np.where(np.abs(z) > synth.Z_HALF[l], z - np.sign(z) * synth.PIXEL, z)
+            pts = np.concatenate([pts, np.stack([x, y, z], 1)])
+            fr.append(pts[rng.permutation(len(pts))])
+        frames.append(fr)
+    fs = Frames(frames)
+    assert np.array_equal(np.diff(fs.layer_offsets).reshape(-1, 4), np.asarray(LIMIT_FILL))
+    return fs
+
+
+def test_layers_at_the_hit_limit(lib):
+    """Layers at the hit limit, one below and one above it, with the paper's
+    caps and with lifted caps (then the full-size frames reach the vertex
+    stage), in the plain form and in the batched form."""
+    import torch
+    fs = limit_frames()
+    over = np.asarray([max(w) > 128 for w in LIMIT_FILL])
+    for what, p in (("limit frames", default_params()), ("limit frames lifted", lifted_caps())):
+        orc, flags, counts = check(lib, fs, p, what)
+        assert np.array_equal((flags & 32) != 0, over)
+        dh = lib.to_device(fs)
+        a = lib.select_frames(dh, p)
+        for fuse in (0, 1):
+            b = lib.BatchedSelector(dh, p, waves_per_cu=4, frames_per_claim=1, fuse_fits=fuse, steal_percent=50)
+            b.run()
+            torch.cuda.synchronize()
+            fa, ca, va = a.result()
+            fb, cb, vb = b.result()
+            assert np.array_equal(fa, fb) and np.array_equal(ca, cb)
+            assert np.array_equal(np.nan_to_num(va), np.nan_to_num(vb))
+            assert b.counters()[2] == 0
+    assert counts[:, 0].max() > 2000 and counts[:, 2].max() > 500 and (flags & 16).any()
+
+
 def test_empty_and_tiny_frames(lib):
     from helpers import Frames
     frames = [[[], [], [], []],
