@@ -118,3 +118,32 @@ def test_strided_inputs(setup):
     gb = lib.align_backward(dh, tf, tht, p, w).cpu().numpy()
     # float64 accumulation in arbitrary atomic order: equal up to its rounding
     assert np.allclose(ga, gb, rtol=1e-6, atol=1e-6 * np.abs(ga).max())
+
+
+def test_empty_and_single_triplet(setup):
+    """No triplets: an empty chi2, a zero gradient (also through autograd).
+    One triplet: chi2 and gradient against the oracle (one block of the
+    backward pass has work, every other block contributes zero rows)."""
+    import torch
+    lib, fs, p, trip, dh = setup
+    S = synth.N_SENSORS
+    rng = np.random.default_rng(5)
+    th32 = np.concatenate([rng.normal(0, 0.02, (S, 3)), rng.normal(0, 2e-4, (S, 1))], 1).astype(np.float32)
+    thc = torch.from_numpy(th32).cuda()
+    none = torch.zeros((0, 3), dtype=torch.int32, device="cuda")
+    assert lib.align_chi2(dh, none, thc, p).numel() == 0
+    g0 = lib.align_backward(dh, none, thc, p, torch.zeros(0, dtype=torch.float32, device="cuda"))
+    assert torch.count_nonzero(g0).item() == 0
+    th = thc.clone().requires_grad_(True)
+    lib.align_chi2_autograd(th, dh, none, p).sum().backward()
+    assert th.grad is not None and torch.count_nonzero(th.grad).item() == 0
+    one = trip[len(trip) // 2:len(trip) // 2 + 1]
+    c1 = lib.align_chi2(dh, torch.from_numpy(one).cuda(), thc, p).cpu().numpy()
+    L1, gref = oracle.align_loss_grad(fs, one, th32.astype(np.float64), p)
+    assert c1.shape == (1,) and abs(float(c1[0]) - L1) <= 1e-4 * max(L1, 1.0)
+    g1 = lib.align_backward(dh, torch.from_numpy(one).cuda(), thc, p,
+                            torch.ones(1, dtype=torch.float32, device="cuda")).cpu().numpy()
+    touched = np.unique(fs.sensor[one.ravel()].astype(np.int64))
+    assert np.count_nonzero(np.abs(g1).sum(1)) <= 3
+    assert set(np.flatnonzero(np.abs(g1).sum(1))) <= set(touched.tolist())
+    assert np.linalg.norm(g1 - gref) <= 1e-3 * np.linalg.norm(gref)
