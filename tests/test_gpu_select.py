@@ -369,6 +369,41 @@ def test_fit_triplets(lib):
         assert np.max(err) <= 1e-4, (k, float(np.max(err)), int(np.argmax(err)))
 
 
+def test_fit_triplets_degenerate_and_out_of_range(lib):
+    """Triplets the fit cannot take give NaN in all eight fields: collinear
+    in the transverse plane (along x, along y), a repeated hit, and hit
+    indices outside [0, n_hits) (a kernel-side bounds check, no read);
+    an ordinary triplet among them matches the oracle; no triplets is a
+    valid call."""
+    import torch
+    from helpers import Frames
+    fs = Frames([[[(25.0, 0.0, 1.0), (0.0, 25.0, 1.0)],
+                  [(31.0, 0.0, 2.0), (0.0, 31.0, 2.0), (31.0, 0.5, 2.0)],
+                  [(73.0, 0.0, 5.0), (0.0, 73.0, 5.0), (73.0, 2.0, 5.0)], []]])
+    big, small = np.iinfo(np.int32).max, np.iinfo(np.int32).min
+    trip = np.array([[0, 2, 5], [1, 3, 6], [0, 0, 5], [0, 4, 7], [-1, 2, 5], [0, 2, fs.n_hits],
+                     [0, big, 7], [small, 4, 7]], np.int32)
+    print(f"case: fit_triplets degenerate, n={len(trip)}", flush=True)
+    dh = lib.to_device(fs)
+    p = default_params()
+    out = lib.fit_triplets(dh, torch.from_numpy(trip).cuda(), p).cpu().numpy()
+    good = np.zeros(len(trip), bool)
+    good[3] = True
+    assert np.all(np.isnan(out[~good]))
+    h = np.stack([np.stack([fs.x[trip[good, k]], fs.y[trip[good, k]], fs.z[trip[good, k]]], 1)
+                  for k in range(3)], 1)
+    ref, rok = oracle.fit(h.astype(np.float64), p)
+    assert rok.all()
+    names = ["kappa", "sigma2_kappa", "chi2", "r_star", "sigma2_r", "rtc", "theta1", "theta2"]
+    for i, k in enumerate(names):
+        floor = 1.0 if k == "chi2" else 0.0
+        assert abs(float(out[good][0, i]) - ref[k][0]) <= 1e-4 * max(abs(ref[k][0]), floor), k
+    # the oracle rejects the in-range degenerate ones as well
+    hd = np.stack([np.stack([fs.x[trip[:3, k]], fs.y[trip[:3, k]], fs.z[trip[:3, k]]], 1) for k in range(3)], 1)
+    assert not oracle.fit(hd.astype(np.float64), p)[1].any()
+    assert lib.fit_triplets(dh, torch.zeros((0, 3), dtype=torch.int32, device="cuda"), p).shape == (0, 8)
+
+
 def test_vertex_entry_point(lib):
     """mu3e_vertex on the oracle's accepted tracks reproduces the oracle's
     vertex decisions for frames without an overflow."""
@@ -392,6 +427,47 @@ def test_vertex_entry_point(lib):
     v = ok & ((orc.flags & 16) != 0)
     assert v.sum() > 100
     assert np.allclose(gv[v, :3], orc.vertex[v, :3], rtol=1e-4, atol=1e-3)
+
+
+def test_vertex_entry_point_malformed(lib):
+    """mu3e_vertex on hand-made track ranges: a track with a hit index
+    outside [0, n_hits) is ignored (the frame gives what it gives without
+    that track), a decreasing range and a range past n_tracks form no
+    triple (no flag, no combination, NaN vertex); the other frames match
+    the oracle."""
+    import torch
+    cfg = dataclasses.replace(synth.CONFIGS[1], lam=1.0, noise_per_layer=1, signal_frac=0.6)
+    fs = synth.generate(cfg, n_frames=300, salt=11)
+    p = default_params()
+    orc = oracle.run(fs, p)
+    k = orc.tracks[(orc.tracks[:, 6] == 1) & (orc.tracks[:, 7] == 0)]
+    cand = [f for f in range(fs.n_frames) if orc.amb[f] == 0 and (orc.flags[f] & (2 | 4 | 32)) == 0
+            and (orc.flags[f] & 16) and (k[:, 0] == f).sum() >= 4]
+    assert len(cand) >= 2
+    fa, fb = cand[0], cand[1]
+    ta = k[k[:, 0] == fa][:, 1:5].astype(np.int32)
+    tb = k[k[:, 0] == fb][:, 1:5].astype(np.int32)
+    bad = ta.copy()
+    bad[1, 2] = fs.n_hits
+    bad2 = ta.copy()
+    bad2[1, 0] = -1
+    drop = np.delete(ta, 1, axis=0)
+    hits = np.concatenate([ta, bad, bad2, drop, tb])
+    n = len(hits)
+    ends = np.cumsum([len(ta), len(bad), len(bad2), len(drop), len(tb)])
+    off = np.array([0, *ends, 5, n + 7], np.int32)       # frame 5 decreasing, frame 6 past the end
+    print(f"case: vertex malformed, {n} tracks, offsets {off.tolist()}", flush=True)
+    dh = lib.to_device(fs)
+    gf, gc, gv = lib.vertex(dh, torch.from_numpy(hits).cuda(), torch.from_numpy(off).cuda(), p)
+    gf, gc, gv = gf.cpu().numpy(), gc.cpu().numpy(), gv.cpu().numpy()
+    for g, f in ((0, fa), (4, fb)):
+        assert gf[g] & 24 == orc.flags[f] & 24 and gc[g] == orc.counts[f, 2]
+        assert np.allclose(gv[g, :3], orc.vertex[f, :3], rtol=1e-4, atol=1e-3)
+    for g in (1, 2):
+        assert gf[g] == gf[3] and gc[g] == gc[3]
+        assert np.array_equal(np.isnan(gv[g]), np.isnan(gv[3]))
+        assert np.allclose(gv[g], gv[3], rtol=1e-6, atol=1e-6, equal_nan=True)
+    assert np.all(gf[5:] == 0) and np.all(gc[5:] == 0) and np.all(np.isnan(gv[5:]))
 
 
 def test_deterministic_outputs(lib):
