@@ -225,6 +225,43 @@ def test_batched_empty_and_tiny(lib):
             assert b.counters()[2] == 0
 
 
+def test_malformed_layer_offsets(lib):
+    """Frames whose layer offsets are negative, decreasing or beyond n_hits
+    are skipped (no flag, no count) and reported in status bit 4, in both
+    forms; every other frame gives what it gives with correct offsets."""
+    import torch
+    fs = synth.generate(2, n_frames=300)
+    p = default_params()
+    lo = fs.layer_offsets.copy()
+    F = fs.n_frames
+    lo[4 * 10 + 1] = lo[4 * 10] - 1              # layer 0 count negative
+    lo[4 * 20 + 2] = lo[4 * 20 + 1] - 3          # layer 1 count negative
+    lo[4 * 30 + 3] = lo[4 * 30 + 4] + 2          # layer 3 count negative
+    lo[4 * 40] = -1                              # frame 40 starts below 0, frame 39 ends below its start
+    lo[4 * F] = fs.n_hits + 5                    # the last frame ends beyond n_hits
+    skip = np.zeros(F, bool)
+    skip[[10, 20, 30, 39, 40, F - 1]] = True
+    bad = dataclasses.replace(fs, layer_offsets=lo)
+    print(f"case: malformed offsets, frames {np.flatnonzero(skip).tolist()}", flush=True)
+    ref = lib.select_frames(lib.to_device(fs), p)
+    dh = lib.to_device(bad)
+    a = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    fr, cr, vr = ref.result()
+    fa, ca, va = a.result()
+    assert np.all(fa[skip] == 0) and np.all(ca[skip] == 0)
+    assert np.array_equal(fa[~skip], fr[~skip]) and np.array_equal(ca[~skip], cr[~skip])
+    assert np.array_equal(np.nan_to_num(va[~skip]), np.nan_to_num(vr[~skip]))
+    assert a.counters()[2] & 4 and not ref.counters()[2] & 4
+    for fuse in (0, 1):
+        b = lib.BatchedSelector(dh, p, waves_per_cu=4, frames_per_claim=2, fuse_fits=fuse, steal_percent=50)
+        b.run()
+        torch.cuda.synchronize()
+        fb, cb, vb = b.result()
+        assert np.array_equal(fa, fb) and np.array_equal(ca, cb)
+        assert b.counters()[2] & 4
+
+
 def test_misaligned_frames(lib):
     check(lib, synth.generate(5, n_frames=2000), default_params(), "cfg5[:2000]")
 
