@@ -79,21 +79,26 @@ class Hip:
         self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         self.L.hipEventSynchronize.argtypes = [ctypes.c_void_p]
 
+    @staticmethod
+    def _ok(status, what):
+        if status != 0:
+            raise RuntimeError(f"{what} failed with HIP error {status}")
+
     def events(self, n):
         arr = (ctypes.c_void_p * n)()
         for i in range(n):
             e = ctypes.c_void_p()
-            assert self.L.hipEventCreate(ctypes.byref(e)) == 0
+            self._ok(self.L.hipEventCreate(ctypes.byref(e)), "hipEventCreate")
             arr[i] = e
         return arr
 
     def record(self, e, stream):
-        assert self.L.hipEventRecord(e, ctypes.c_void_p(stream.cuda_stream)) == 0
+        self._ok(self.L.hipEventRecord(e, ctypes.c_void_p(stream.cuda_stream)), "hipEventRecord")
 
     def elapsed(self, a, b) -> float:
         ms = ctypes.c_float()
-        assert self.L.hipEventSynchronize(b) == 0
-        assert self.L.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        self._ok(self.L.hipEventSynchronize(b), "hipEventSynchronize")
+        self._ok(self.L.hipEventElapsedTime(ctypes.byref(ms), a, b), "hipEventElapsedTime")
         return ms.value
 
 

@@ -214,7 +214,9 @@ class Selector:
         """events: optional ctypes array of 5 hipEvent_t recorded between the
         stage kernels."""
         L = load()
-        assert hits.n_frames == self.n_frames
+        if hits.n_frames != self.n_frames:
+            raise ValueError(f"hits hold {hits.n_frames} frames; the selector's outputs are sized for "
+                             f"{self.n_frames}")
         hs = hits.struct()
         if events is None:
             st = L.mu3e_select_frames(ctypes.byref(hs), ctypes.byref(self.params), _ptr(self.flags),
@@ -300,7 +302,8 @@ class BatchedSelector(Selector):
         """events: optional ctypes array of 4 hipEvent_t; then the plan's
         kernels are launched directly (no graph) with the events around the
         persistent kernel and the fit kernel (mu3e_plan_run_timed)."""
-        assert hits is None or hits is self.hits, "a plan is bound to the hits it was created with"
+        if hits is not None and hits is not self.hits:
+            raise ValueError("a plan is bound to the hits it was created with")
         if events is None:
             _check(load().mu3e_plan_run(self.plan, _stream(stream)), "mu3e_plan_run")
         else:

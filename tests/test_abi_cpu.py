@@ -112,3 +112,18 @@ def test_binding_fails_loudly_without_library():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0 and out.stdout.startswith("raised"), out.stdout + out.stderr
+
+
+def test_selector_rejects_other_frame_count(L):
+    """The binding refuses hits with more (or fewer) frames than a
+    selector's outputs are sized for, before any call into the library
+    (host tensors: nothing reaches a GPU)."""
+    import torch  # noqa: F401
+    from paper_2206_11535_amd import lib, synth
+    from paper_2206_11535_amd.params import default_params
+    fs = synth.generate(2, n_frames=20)
+    hits = lib.to_device(fs, device="cpu")
+    for n in (10, 30):
+        sel = lib.Selector(n, default_params(), device="cpu")
+        with pytest.raises(ValueError, match="frames"):
+            sel.run(hits)
