@@ -147,3 +147,38 @@ def test_empty_and_single_triplet(setup):
     assert np.count_nonzero(np.abs(g1).sum(1)) <= 3
     assert set(np.flatnonzero(np.abs(g1).sum(1))) <= set(touched.tolist())
     assert np.linalg.norm(g1 - gref) <= 1e-3 * np.linalg.norm(gref)
+
+
+def test_invalid_indices_and_sensors(setup):
+    """A triplet with a hit index outside [0, n_hits), or a hit on a sensor
+    beyond theta's rows, gives NaN chi2 and adds nothing to the gradient
+    (bounds checks in the kernels: nothing outside the buffers is read)."""
+    import torch
+    lib, fs, p, trip, dh = setup
+    S = synth.N_SENSORS
+    rng = np.random.default_rng(6)
+    th32 = np.concatenate([rng.normal(0, 0.02, (S, 3)), rng.normal(0, 2e-4, (S, 1))], 1).astype(np.float32)
+    sub = trip[rng.choice(len(trip), 2000, replace=False)]
+    bad = np.array([[-1, sub[0, 1], sub[0, 2]], [sub[1, 0], sub[1, 1], fs.n_hits]], np.int32)
+    mixed = np.concatenate([sub, bad])
+    cm = lib.align_chi2(dh, torch.from_numpy(mixed).cuda(), torch.from_numpy(th32).cuda(), p).cpu().numpy()
+    cs = lib.align_chi2(dh, torch.from_numpy(sub).cuda(), torch.from_numpy(th32).cuda(), p).cpu().numpy()
+    assert np.all(np.isnan(cm[-2:])) and np.array_equal(cm[:-2], cs)
+    ones = lambda n: torch.ones(n, dtype=torch.float32, device="cuda")
+    gm = lib.align_backward(dh, torch.from_numpy(mixed).cuda(), torch.from_numpy(th32).cuda(), p, ones(len(mixed)))
+    gs = lib.align_backward(dh, torch.from_numpy(sub).cuda(), torch.from_numpy(th32).cuda(), p, ones(len(sub)))
+    assert torch.allclose(gm, gs, rtol=1e-6, atol=1e-9 * float(gs.abs().max()))
+    # theta with fewer rows than the largest sensor id of the hits
+    smax = fs.sensor[sub].astype(np.int64).max(axis=1)
+    cut = int(np.median(smax))
+    inside = smax < cut
+    assert 100 < inside.sum() < len(sub) - 100
+    ts = torch.from_numpy(np.ascontiguousarray(th32[:cut])).cuda()
+    cc = lib.align_chi2(dh, torch.from_numpy(sub).cuda(), ts, p).cpu().numpy()
+    assert np.all(np.isnan(cc[~inside])) and np.array_equal(cc[inside], cs[inside])
+    gc = lib.align_backward(dh, torch.from_numpy(sub).cuda(), ts, p, ones(len(sub)))
+    gi = lib.align_backward(dh, torch.from_numpy(np.ascontiguousarray(sub[inside])).cuda(),
+                            torch.from_numpy(th32).cuda(), p, ones(int(inside.sum())))
+    assert gc.shape == (cut, 4)
+    assert torch.allclose(gc, gi[:cut], rtol=1e-6, atol=1e-9 * float(gi.abs().max()))
+    assert torch.count_nonzero(gi[cut:]).item() == 0
