@@ -657,12 +657,20 @@ def test_batched_shapes_and_repeat(lib, w, c, fuse, steal):
     ref = lib.select_frames(dh, p)
     print(f"case: batched shape {w} waves/CU, {c} frames/claim, fused={fuse}, steal={steal}%", flush=True)
     b = lib.BatchedSelector(dh, p, waves_per_cu=w, frames_per_claim=c, fuse_fits=fuse, steal_percent=steal)
-    for rep in range(2):
+    for rep in range(3):
+        # outputs overwritten with sentinels, so that every replay of the
+        # graph must write them all again; eager work between the replays
+        b.flags.fill_(-1)
+        b.counts.fill_(-1)
+        b.vertex.fill_(7.0)
         b.run()
         torch.cuda.synchronize()
         fr, cr, vr = ref.result()
         fb, cb, vb = b.result()
         assert np.array_equal(fr, fb) and np.array_equal(cr, cb), (w, c, rep)
+        assert np.array_equal(np.nan_to_num(vr), np.nan_to_num(vb)), (w, c, rep)
+        ref.run(dh)
+        torch.cuda.synchronize()
     # the eager, event-bracketed launch of the same plan (outputs cleared first)
     import ctypes
     hip = ctypes.CDLL("libamdhip64.so.7")
