@@ -186,6 +186,20 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t *hits, const mu3e_params_
 mu3e_status mu3e_fit_triplets(const mu3e_hits_t *hits, const int32_t *trip, int32_t n,
                               const mu3e_params_t *params, float *out, hipStream_t stream);
 
+/* Adjoint of the single triplet fit (Section IV-B: the chi2 of the
+ * linearised multiple-scattering fit) with respect to the hit coordinates:
+ * grad_xyz[n_hits][3] += sum_t grad_chi2[t] * d chi2_t / d(x, y, z) over the
+ * three hits of each triplet trip[n][3].  grad_xyz is accumulated, not
+ * overwritten (zero it first for a plain gradient); the additions are
+ * float32 atomics, so their order, and the last bits, vary between calls.
+ * The forward fit is recomputed (nothing is saved between the calls); its
+ * discrete choices (minor arc, branches) stay fixed.  Degenerate triplets
+ * and triplets with a hit index outside [0, n_hits) add nothing.  Caller
+ * owns all buffers; n = 0 is a valid call that launches nothing. */
+mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t *hits, const int32_t *trip, int32_t n,
+                                       const mu3e_params_t *params, const float *grad_chi2,
+                                       float *grad_xyz, hipStream_t stream);
+
 /* Tracks grouped by frame: frame f owns tracks [frame_offsets[f],
  * frame_offsets[f+1]) of hit[n_tracks][4] (global hit indices, layers 0..3). */
 typedef struct {

@@ -1506,6 +1506,31 @@ k_fit(const float* __restrict__ X, const float* __restrict__ Y, const float* __r
 }
 
 
+// Adjoint of the single triplet fit: for every triplet, grad_chi2[t] times
+// the derivative of its chi2 with respect to the coordinates of its three
+// hits is added to grad[hit][3] (float32 atomics: the order of the additions
+// is not fixed).  Degenerate triplets and out-of-range indices add nothing.
+__global__ void __launch_bounds__(256)
+k_fit_bwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
+          const int32_t* __restrict__ trip, int n, Consts C, const float* __restrict__ gchi2,
+          float* __restrict__ grad) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int g[3] = {trip[3 * t], trip[3 * t + 1], trip[3 * t + 2]};
+    if ((unsigned)g[0] >= (unsigned)n_hits || (unsigned)g[1] >= (unsigned)n_hits ||
+        (unsigned)g[2] >= (unsigned)n_hits)
+      continue;
+    double h[9], d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+      h[3 * k] = X[g[k]];
+      h[3 * k + 1] = Y[g[k]];
+      h[3 * k + 2] = Z[g[k]];
+    }
+    float c;
+    if (!fit_chi2_adjoint<float>(h, C, gchi2[t], c, d)) continue;
+    for (int k = 0; k < 9; ++k) atomicAdd(&grad[3 * g[k / 3] + k % 3], (float)d[k]);
+  }
+}
+
 // ============================================================== alignment
 // Summed triplet-fit chi2 under per-sensor alignment (tx, ty, tz, alpha):
 // a hit h on sensor s is moved to R_z(alpha_s) h + t_s (in float64) and the
@@ -1871,6 +1896,22 @@ mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, co
   const int g = F < cus * 16 ? F : cus * 16;
   hipLaunchKernelGGL(k_vframes_range, dim3(g), dim3(kWave), 0, stream, F, n, C, tracks->frame_offsets, vt, vok,
                      frame_flags, frame_combos, frame_vertex);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t* hits, const int32_t* trip, int32_t n,
+                                       const mu3e_params_t* params, const float* grad_chi2, float* grad_xyz,
+                                       hipStream_t stream) {
+  if (!hits || n < 0 || !params ||
+      (n > 0 && (!trip || !grad_chi2 || !grad_xyz || !hits->x || !hits->y || !hits->z)))
+    return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (n == 0) return MU3E_OK;
+  const int cus = device_cus();
+  const int blocks = (n + 255) / 256 < cus * 8 ? (n + 255) / 256 : cus * 8;
+  hipLaunchKernelGGL(k_fit_bwd, dim3(blocks), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->n_hits, trip,
+                     n, C, grad_chi2, grad_xyz);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 

@@ -108,6 +108,8 @@ def load(path: str = LIB_PATH):
                                            ctypes.POINTER(Debug), P, P]
     L.mu3e_fit_triplets.restype = ctypes.c_int
     L.mu3e_fit_triplets.argtypes = [ctypes.POINTER(Hits), P, I, ctypes.POINTER(Params), P, P]
+    L.mu3e_fit_triplets_backward.restype = ctypes.c_int
+    L.mu3e_fit_triplets_backward.argtypes = [ctypes.POINTER(Hits), P, I, ctypes.POINTER(Params), P, P, P]
     L.mu3e_vertex_workspace_size.restype = Z
     L.mu3e_vertex_workspace_size.argtypes = [I]
     L.mu3e_vertex.restype = ctypes.c_int
@@ -335,6 +337,28 @@ def fit_triplets(hits: DeviceHits, trip, params: dict, stream=None):
     _check(L.mu3e_fit_triplets(ctypes.byref(hs), _ptr(trip), n, ctypes.byref(pp), _ptr(out), _stream(stream)),
            "mu3e_fit_triplets")
     return out[:n]
+
+
+def fit_triplets_backward(hits: DeviceHits, trip, params: dict, grad_chi2, grad_xyz=None, stream=None):
+    """d(sum_t grad_chi2[t] chi2_t) / d(hit x, y, z), float32 [n_hits, 3]
+    (added to grad_xyz when given, else to a new zero tensor)."""
+    import torch
+    L = load()
+    trip = _dev(trip, torch.int32, (3,), "trip")
+    grad_chi2 = _dev(grad_chi2, torch.float32, (), "grad_chi2")
+    n = int(trip.shape[0])
+    if int(grad_chi2.shape[0]) != n:
+        raise ValueError("grad_chi2: one entry per triplet expected")
+    if grad_xyz is None:
+        grad_xyz = torch.zeros((max(hits.n_hits, 1), 3), dtype=torch.float32, device=trip.device)
+    elif (not isinstance(grad_xyz, torch.Tensor) or grad_xyz.dtype != torch.float32 or not grad_xyz.is_cuda
+          or tuple(grad_xyz.shape) != (hits.n_hits, 3) or not grad_xyz.is_contiguous()):
+        raise ValueError("grad_xyz: a contiguous float32 GPU tensor [n_hits, 3] expected")
+    hs = hits.struct()
+    pp = make_params(params)
+    _check(L.mu3e_fit_triplets_backward(ctypes.byref(hs), _ptr(trip), n, ctypes.byref(pp), _ptr(grad_chi2),
+                                        _ptr(grad_xyz), _stream(stream)), "mu3e_fit_triplets_backward")
+    return grad_xyz[:hits.n_hits]
 
 
 def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=None):

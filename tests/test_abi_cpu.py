@@ -79,6 +79,9 @@ def test_host_validation(L):
     # fit: negative n, null triplets
     assert L.mu3e_fit_triplets(ctypes.byref(h), None, -1, ctypes.byref(p), None, None) == -1
     assert L.mu3e_fit_triplets(ctypes.byref(h), None, 5, ctypes.byref(p), 1, None) == -1
+    assert L.mu3e_fit_triplets_backward(ctypes.byref(h), None, -1, ctypes.byref(p), None, None, None) == -1
+    assert L.mu3e_fit_triplets_backward(ctypes.byref(h), None, 5, ctypes.byref(p), 1, 1, None) == -1
+    assert L.mu3e_fit_triplets_backward(None, None, 0, ctypes.byref(p), None, None, None) == -1
     # vertex: null tracks, too small workspace
     assert L.mu3e_vertex(ctypes.byref(h), None, ctypes.byref(p), 1, 1, 1, 1, 1 << 20, None) == -1
     tr = lib.Tracks(80, 96, 4, 1000)

@@ -441,6 +441,59 @@ def test_fit_triplets_degenerate_and_out_of_range(lib):
     assert lib.fit_triplets(dh, torch.zeros((0, 3), dtype=torch.int32, device="cuda"), p).shape == (0, 8)
 
 
+def test_fit_triplets_backward(lib):
+    """Adjoint of the fit chi2 with respect to the hit coordinates against
+    FP64 central differences of the oracle's fit chi2 (step 1e-4 mm), on
+    true triplets sharing hits, with random upstream gradients; an invalid
+    triplet adds nothing, a given buffer is added to, n = 0 is valid."""
+    import torch
+    fs = synth.generate(2, n_frames=1500)
+    tt, _, tab = synth.true_triplets(fs)
+    t2 = tab[np.all(tab[:, 1:4] >= 0, axis=1)][:, 1:4]
+    trip = np.concatenate([tt, t2]).astype(np.int32)
+    p = default_params()
+    h = np.stack([np.stack([fs.x[trip[:, k]], fs.y[trip[:, k]], fs.z[trip[:, k]]], 1) for k in range(3)], 1)
+    h = h.astype(np.float64)
+    ref, rok = oracle.fit(h, p)
+    trip, h = trip[rok], h[rok]
+    rng = np.random.default_rng(11)
+    w = rng.uniform(0.0, 2.0, len(trip))
+    eps = 1e-4
+    hp = np.repeat(h[:, None], 9, 1).copy()
+    hm = hp.copy()
+    for j in range(9):
+        hp[:, j, j // 3, j % 3] += eps
+        hm[:, j, j // 3, j % 3] -= eps
+    cp, okp = oracle.fit(hp.reshape(-1, 3, 3), p)
+    cm, okm = oracle.fit(hm.reshape(-1, 3, 3), p)
+    assert okp.all() and okm.all()
+    d = ((cp["chi2"] - cm["chi2"]) / (2 * eps)).reshape(-1, 9) * w[:, None]
+    gref = np.zeros((fs.n_hits, 3))
+    for k in range(3):
+        np.add.at(gref, trip[:, k], d[:, 3 * k:3 * k + 3])
+    bad = np.array([[-1, trip[0, 1], trip[0, 2]]], np.int32)
+    print(f"case: fit_triplets_backward n={len(trip)}", flush=True)
+    dh = lib.to_device(fs)
+    tg = torch.from_numpy(np.concatenate([trip, bad])).cuda()
+    wg = torch.from_numpy(np.concatenate([w, [1.0]]).astype(np.float32)).cuda()
+    g = lib.fit_triplets_backward(dh, tg, p, wg)
+    torch.cuda.synchronize()
+    gn = g.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(gn - gref) / np.linalg.norm(gref)
+    floor = 1e-3 * np.abs(gref).max()
+    elem = np.max(np.abs(gn - gref) / np.maximum(np.abs(gref), floor))
+    print("fit adjoint vs central differences: norm-wise", err, "element-wise (floored)", elem, flush=True)
+    assert err <= 1e-3 and elem <= 1e-2
+    used = np.zeros(fs.n_hits, bool)
+    used[trip.ravel()] = True
+    assert np.count_nonzero(gn[~used]) == 0
+    g2 = lib.fit_triplets_backward(dh, tg, p, wg, grad_xyz=g.clone())
+    assert torch.allclose(g2, 2 * g, rtol=1e-5, atol=1e-6 * float(g.abs().max()))
+    z = lib.fit_triplets_backward(dh, torch.zeros((0, 3), dtype=torch.int32, device="cuda"), p,
+                                  torch.zeros(0, dtype=torch.float32, device="cuda"))
+    assert z.shape == (fs.n_hits, 3) and torch.count_nonzero(z).item() == 0
+
+
 def test_vertex_entry_point(lib):
     """mu3e_vertex on the oracle's accepted tracks reproduces the oracle's
     vertex decisions for frames without an overflow."""
