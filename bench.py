@@ -52,7 +52,7 @@ FLOPS_PAIR01, FLOPS_PAIR12, FLOPS_JOIN, FLOPS_RTC = 4, 6, 3, 24
 # (null once the source changes).
 TRAFFIC = {
     # profiles/nominal_hbm_traffic.md: 88.70 MB read + 23.21 MB written per launch
-    "e911b91c88bc2837|k_batched": 111905412,
+    "cf79a04bb751ce55|k_batched": 111892060,
 }
 
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X float32 vector (published)
