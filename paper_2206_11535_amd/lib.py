@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 
@@ -457,3 +457,41 @@ def align_chi2_autograd(theta, hits: DeviceHits, trip, params: dict):
     if _align_fn is None:
         _align_fn = _autograd()
     return _align_fn.apply(theta, hits, trip, params)
+
+
+def _fit_autograd():
+    import torch
+
+    class FitChi2(torch.autograd.Function):
+        """chi2_min[n] of explicit triplets as a function of the hit
+        coordinates x, y, z [n_hits] (float32 GPU tensors); forward is
+        mu3e_fit_triplets, backward the hand-written adjoint
+        (mu3e_fit_triplets_backward).  Degenerate triplets give NaN and no
+        gradient."""
+
+        @staticmethod
+        def forward(ctx, x, y, z, hits, trip, params):
+            h = replace(hits, x=x.detach().contiguous().float(), y=y.detach().contiguous().float(),
+                        z=z.detach().contiguous().float())
+            ctx.h, ctx.trip, ctx.params = h, trip, params
+            return fit_triplets(h, trip, params)[:, 2].contiguous()
+
+        @staticmethod
+        def backward(ctx, grad_chi2):
+            g = fit_triplets_backward(ctx.h, ctx.trip, ctx.params, grad_chi2.contiguous().float())
+            return g[:, 0].contiguous(), g[:, 1].contiguous(), g[:, 2].contiguous(), None, None, None
+
+    return FitChi2
+
+
+_fit_fn = None
+
+
+def fit_chi2_autograd(x, y, z, hits: DeviceHits, trip, params: dict):
+    """Differentiable chi2_min[n] of the triplets trip [n, 3] with respect to
+    the hit coordinates x, y, z [n_hits] (torch.autograd.Function around the
+    C ABI; the other fields of `hits` are taken as they are)."""
+    global _fit_fn
+    if _fit_fn is None:
+        _fit_fn = _fit_autograd()
+    return _fit_fn.apply(x, y, z, hits, trip, params)

@@ -494,6 +494,34 @@ def test_fit_triplets_backward(lib):
     assert z.shape == (fs.n_hits, 3) and torch.count_nonzero(z).item() == 0
 
 
+def test_fit_chi2_autograd(lib):
+    """The autograd wrapper over the hit coordinates: chi2 as from
+    mu3e_fit_triplets, gradients as from mu3e_fit_triplets_backward, and a
+    small step along the gradient lowers the summed chi2."""
+    import torch
+    fs = synth.generate(2, n_frames=300)
+    tt, _, _ = synth.true_triplets(fs)
+    trip = torch.from_numpy(np.ascontiguousarray(tt, dtype=np.int32)).cuda()
+    p = default_params()
+    dh = lib.to_device(fs)
+    x, y, z = (t.clone().requires_grad_(True) for t in (dh.x, dh.y, dh.z))
+    c = lib.fit_chi2_autograd(x, y, z, dh, trip, p)
+    ref = lib.fit_triplets(dh, trip, p)[:, 2]
+    ok = torch.isfinite(ref)
+    assert ok.sum() > 500 and torch.equal(c[ok], ref[ok])
+    w = torch.where(ok, torch.rand(len(ok), device="cuda"), torch.zeros_like(ref))
+    (torch.nan_to_num(c) * w).sum().backward()
+    g = lib.fit_triplets_backward(dh, trip, p, w)
+    gxyz = torch.stack([x.grad, y.grad, z.grad], 1)
+    assert torch.allclose(gxyz, g, rtol=1e-5, atol=1e-6 * float(g.abs().max()))
+    with torch.no_grad():
+        step = 1e-4 / float(gxyz.abs().max())
+        h2 = lib.DeviceHits(x - step * x.grad, y - step * y.grad, z - step * z.grad, dh.layer, dh.sensor,
+                            dh.layer_offsets, dh.n_frames, dh.n_hits)
+        after = lib.fit_triplets(h2, trip, p)[:, 2]
+    assert float((after[ok] * w[ok]).sum()) < float((ref[ok] * w[ok]).sum())
+
+
 def test_vertex_entry_point(lib):
     """mu3e_vertex on the oracle's accepted tracks reproduces the oracle's
     vertex decisions for frames without an overflow."""
