@@ -491,6 +491,11 @@ def fit_chi2_autograd(x, y, z, hits: DeviceHits, trip, params: dict):
     """Differentiable chi2_min[n] of the triplets trip [n, 3] with respect to
     the hit coordinates x, y, z [n_hits] (torch.autograd.Function around the
     C ABI; the other fields of `hits` are taken as they are)."""
+    import torch
+    for name, t in (("x", x), ("y", y), ("z", z)):
+        if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+                or tuple(t.shape) != (hits.n_hits,)):
+            raise ValueError(f"{name}: a float32 GPU tensor [n_hits] = [{hits.n_hits}] expected")
     global _fit_fn
     if _fit_fn is None:
         _fit_fn = _fit_autograd()

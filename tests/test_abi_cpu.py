@@ -130,3 +130,20 @@ def test_selector_rejects_other_frame_count(L):
         sel = lib.Selector(n, default_params(), device="cpu")
         with pytest.raises(ValueError, match="frames"):
             sel.run(hits)
+
+
+def test_fit_autograd_rejects_wrong_coordinates(L):
+    """The hit-coordinate autograd wrapper refuses coordinate tensors that
+    are not float32 GPU tensors of length n_hits, before any library call
+    (host tensors here: nothing reaches a GPU)."""
+    import torch
+    from paper_2206_11535_amd import lib, synth
+    from paper_2206_11535_amd.params import default_params
+    fs = synth.generate(2, n_frames=5)
+    hits = lib.to_device(fs, device="cpu")
+    trip = torch.zeros((1, 3), dtype=torch.int32)
+    x = torch.zeros(fs.n_hits - 1)
+    with pytest.raises(ValueError, match="x"):
+        lib.fit_chi2_autograd(x, hits.y, hits.z, hits, trip, default_params())
+    with pytest.raises(ValueError, match="x"):
+        lib.fit_chi2_autograd(hits.x, hits.y, hits.z, hits, trip, default_params())   # host tensors
