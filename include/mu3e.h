@@ -71,7 +71,8 @@ typedef struct {
   const float *x, *y, *z;            /* [n_hits] mm                              */
   const uint16_t *layer, *sensor;    /* [n_hits]                                 */
   const int32_t *layer_offsets;      /* [4*n_frames+1], non-decreasing, [0] = 0  */
-  int32_t n_frames, n_hits;
+  int32_t n_frames, n_hits;          /* both >= 0: every entry point refuses a
+                                        negative count (MU3E_ERR_INVALID_ARG)    */
 } mu3e_hits_t;
 
 typedef struct { float lo, hi; } mu3e_window_t;   /* pass iff lo <= q <= hi */

@@ -14,7 +14,7 @@
 //   Section IV-C  Vertex Fit           the weighted 2D vertex, eq. track-error,
 //                                      the z back-projection, the vertex chi2;
 //                                      Alg. 4
-//   Section V-B   frame flow and the "marked for storage" overflow rule; Alg. 1
+//   Section V-B   frame flow and the rule that an overflowing frame is kept; Alg. 1
 // Readings of silent or garbled passages are listed in the design notes and
 // repeated at the function that applies them.
 //
@@ -118,7 +118,7 @@ inline double highland(double p, double x) {   // projected MS angle, beta = 1
 // ============================================================ Selection Cuts
 // Section IV-A.  The detector is four concentric cylinders: in tan(lambda) and
 // cos(Phi) the transverse radius of a hit is the nominal layer radius (the
-// text's "h_{t,k} = r_{r,i}" is read as r_{t,i}).  d_ij in eq. rt-cut are
+// text's subscript r_{r,i} is read as r_{t,i}, a typo).  d_ij in eq. rt-cut are
 // transverse distances because r_{t,c} is a transverse radius.  The sign of
 // r_{t,c} follows the cross product (h0-h1) x (h2-h1): positive for clockwise
 // (positive charge in B along +z).
@@ -245,7 +245,7 @@ bool triplet_fit(const T* h0, const T* h1, const T* h2, const Params& P, Fit<T>&
 // predicts the layer-3 position; the closest layer-3 hit forms the second
 // triplet.  Reading: the helix is the transverse circumcircle with the z
 // slope of arc 2 per radian of turning; the predicted point is the first
-// crossing of r = R3 reached going forward from h2; "closest" is the 3D
+// crossing of r = R3 reached going forward from h2; the nearest hit is by 3D
 // Euclidean distance with no search window; ties go to the lowest index.
 // Returns false if the circle never reaches r = R3.
 bool predict_l3(const double* h1, const double* h2, const Fit<double>& f, const Params& P, double* out,
@@ -271,6 +271,19 @@ bool predict_l3(const double* h1, const double* h2, const Fit<double>& f, const 
   out[0] = bx; out[1] = by;
   out[2] = h2[2] + best * (h2[2] - h1[2]) / f.phi2;
   return true;
+}
+
+// Section IV-B, "Triplets Fit": the two triplet fits of a track combined.
+// The curvature is the mean of the two kappas weighted by 1/sigma^2_kappa;
+// chi2_global is the sum over both triplets of their quadratic chi2 (the
+// minimum plus the curvature term) evaluated at Rbar = 1/|kbar| (eq.
+// objective-function-global read as a function of the curvature).
+void combine_fits(const Fit<double>& f1, const Fit<double>& f2, double& kbar, double& chi2) {
+  double w1 = 1 / f1.sigma2_kappa, w2 = 1 / f2.sigma2_kappa;
+  kbar = (f1.kappa * w1 + f2.kappa * w2) / (w1 + w2);
+  double rbar = 1 / std::fabs(kbar);
+  chi2 = f1.chi2 + (rbar - f1.r_star) * (rbar - f1.r_star) / f1.sigma2_r
+       + f2.chi2 + (rbar - f2.r_star) * (rbar - f2.r_star) / f2.sigma2_r;
 }
 
 // ============================================================ Vertex
@@ -301,6 +314,21 @@ void track_circle(Track& t, const double* h0, const double* h1, const Params& P)
   t.E = std::sqrt(t.p * t.p + kMe * kMe);
   t.sms0 = highland(t.p, P.xx0 / std::sin(t.theta1));
   t.h0 = h0;
+}
+
+// A track given by its four hits (layers 0..3): both triplet fits, their
+// combination and the transverse circle.  False if a fit fails.
+bool track_from_hits(const double* q, const Params& P, Track& t) {
+  Fit<double> f1, f2;
+  if (!triplet_fit(q, q + 3, q + 6, P, f1) || !triplet_fit(q + 3, q + 6, q + 9, P, f2)) return false;
+  double chi2;
+  combine_fits(f1, f2, t.kbar, chi2);
+  t.chi2 = chi2;
+  t.charge = t.kbar > 0 ? 1 : -1;
+  t.rbar = 1 / std::fabs(t.kbar);
+  t.theta1 = f1.theta1;
+  track_circle(t, q, q + 3, P);
+  return true;
 }
 
 // turning angle travelled backwards from the layer-0 hit to point q
@@ -385,8 +413,7 @@ VertexOut vertex_triple(const Track* T[3], const Params& P) {
       cay[k] = t.cy + t.rt * vy / vn;
       double dphi = back_angle(t, cax[k], cay[k]);
       zz[k] = t.h0[2] - dphi * t.rbar * std::cos(t.theta1);  // z back-projection
-      double s = t.rt * dphi;
-      sg2[k] = t.sms0 * t.sms0 * s * s + P.sigma_pix * P.sigma_pix;
+      sg2[k] = point_sigma2(t, cax[k], cay[k], P);
     }
     if (!ok) continue;
     double wz = 0, mz = 0;
@@ -467,7 +494,8 @@ void process_frame(int f, const float* X, const float* Y, const float* Z, const 
   for (auto& c : sel) n_pass += c.amb ? 0 : 1;
   out.counts[0] = n_pass;                      // sure passes (ambiguous ones excluded)
   out.namb[0] = n_amb_trip;
-  // count semantics: exact; overflow iff count > cap (Section VI-B: "higher than ... 768")
+  // count semantics: exact; overflow iff count > cap (Section VI-B compares the
+  // count against the cap of 768 with a strict inequality)
   int lo_cnt = n_pass, hi_cnt = n_pass + n_amb_trip;
   if (lo_cnt > P.max_triplets) out.flags |= TRIPLET_OVF;
   if (n_amb_trip) out.amb |= TRIPLET_OVF | TRACK_OVF | COMBO_OVF | VERTEX;   // descendants excused
@@ -508,11 +536,9 @@ void process_frame(int f, const float* X, const float* Y, const float* Z, const 
     out.st.tracks_tested++;
     if (!triplet_fit(h1, h2, h3, P, f2)) continue;
     if (f2.sgn != f1.sgn) continue;                          // opposite bending: reject
-    double w1 = 1 / f1.sigma2_kappa, w2 = 1 / f2.sigma2_kappa;
-    double kbar = (f1.kappa * w1 + f2.kappa * w2) / (w1 + w2);
+    double kbar, chi2;
+    combine_fits(f1, f2, kbar, chi2);
     double rbar = 1 / std::fabs(kbar);
-    double chi2 = f1.chi2 + (rbar - f1.r_star) * (rbar - f1.r_star) / f1.sigma2_r
-                + f2.chi2 + (rbar - f2.r_star) * (rbar - f2.r_star) / f2.sigma2_r;
     if (near_edge(chi2, P.chi2_track_max, P.amb)) amb = true;
     bool pass = chi2 < P.chi2_track_max;                     // strict (Section IV-B)
     if (want_lists && (pass || amb))
@@ -738,13 +764,11 @@ void oc_track4(const double* h /*[n][12]*/, int n, const double* params, double*
     ok[i] = 0;
     if (!triplet_fit(q, q + 3, q + 6, P, f1) || !triplet_fit(q + 3, q + 6, q + 9, P, f2)) continue;
     if (f1.sgn != f2.sgn) continue;
-    double w1 = 1 / f1.sigma2_kappa, w2 = 1 / f2.sigma2_kappa;
-    double kbar = (f1.kappa * w1 + f2.kappa * w2) / (w1 + w2);
-    double rbar = 1 / std::fabs(kbar);
+    double kbar, chi2;
+    combine_fits(f1, f2, kbar, chi2);
     out[4 * i] = kbar;
-    out[4 * i + 1] = f1.chi2 + (rbar - f1.r_star) * (rbar - f1.r_star) / f1.sigma2_r
-                   + f2.chi2 + (rbar - f2.r_star) * (rbar - f2.r_star) / f2.sigma2_r;
-    out[4 * i + 2] = f1.theta1; out[4 * i + 3] = rbar;
+    out[4 * i + 1] = chi2;
+    out[4 * i + 2] = f1.theta1; out[4 * i + 3] = 1 / std::fabs(kbar);
     ok[i] = 1;
   }
 }
@@ -759,16 +783,7 @@ void oc_vertex4(const double* h, int n, const double* params, double* out) {
     for (int k = 0; k < 10; ++k) o[k] = std::numeric_limits<double>::quiet_NaN();
     Track T[3];
     bool ok = true;
-    for (int k = 0; k < 3 && ok; ++k) {
-      const double* q = h + 36 * i + 12 * k;
-      Fit<double> f1, f2;
-      if (!triplet_fit(q, q + 3, q + 6, P, f1) || !triplet_fit(q + 3, q + 6, q + 9, P, f2)) { ok = false; break; }
-      double w1 = 1 / f1.sigma2_kappa, w2 = 1 / f2.sigma2_kappa;
-      double kbar = (f1.kappa * w1 + f2.kappa * w2) / (w1 + w2);
-      T[k].charge = kbar > 0 ? 1 : -1;
-      T[k].kbar = kbar; T[k].rbar = 1 / std::fabs(kbar); T[k].theta1 = f1.theta1;
-      track_circle(T[k], q, q + 3, P);
-    }
+    for (int k = 0; k < 3 && ok; ++k) ok = track_from_hits(h + 36 * i + 12 * k, P, T[k]);
     if (!ok) continue;
     const Track* T3[3] = {&T[0], &T[1], &T[2]};
     VertexOut v = vertex_triple(T3, P);
@@ -776,6 +791,50 @@ void oc_vertex4(const double* h, int n, const double* params, double* out) {
     o[5] = T[0].E + T[1].E + T[2].E; o[6] = v.amb;
     o[7] = v.dt; o[8] = v.psum; o[9] = v.reached;
   }
+}
+
+// Per-track vertex-stage quantities of tracks given by four hits:
+// out [n][9] = kbar, rbar, rt, cx, cy, sms0, E, p, theta1; ok[n].
+void oc_track_geom(const double* h /*[n][12]*/, int n, const double* params, double* out, int32_t* ok) {
+  Params P = unpack(params);
+  for (int i = 0; i < n; ++i) {
+    const double* q = h + 12 * i;
+    double* o = out + 9 * i;
+    ok[i] = 0;
+    for (int k = 0; k < 9; ++k) o[k] = std::numeric_limits<double>::quiet_NaN();
+    Track t;
+    if (!track_from_hits(q, P, t)) continue;
+    const double v[9] = {t.kbar, t.rbar, t.rt, t.cx, t.cy, t.sms0, t.E, t.p, t.theta1};
+    std::memcpy(o, v, sizeof v);
+    ok[i] = 1;
+  }
+}
+
+// Backward turning angle from the layer-0 hit to a transverse point q, the
+// path length s = rt * angle and the position variance of eq. track-error at
+// q, for tracks given by four hits: q [n][2], out [n][3]; ok[n].
+void oc_track_point(const double* h /*[n][12]*/, const double* qxy, int n, const double* params, double* out,
+                    int32_t* ok) {
+  Params P = unpack(params);
+  for (int i = 0; i < n; ++i) {
+    const double* q = h + 12 * i;
+    double* o = out + 3 * i;
+    ok[i] = 0;
+    o[0] = o[1] = o[2] = std::numeric_limits<double>::quiet_NaN();
+    Track t;
+    if (!track_from_hits(q, P, t)) continue;
+    const double a = back_angle(t, qxy[2 * i], qxy[2 * i + 1]);
+    o[0] = a;
+    o[1] = t.rt * a;
+    o[2] = point_sigma2(t, qxy[2 * i], qxy[2 * i + 1], P);
+    ok[i] = 1;
+  }
+}
+
+// Distance from (rho, z) points to the double-cone target surface: rz [n][2].
+void oc_cone_distance(const double* rz, int n, const double* params, double* out) {
+  Params P = unpack(params);
+  for (int i = 0; i < n; ++i) out[i] = cone_distance(rz[2 * i], rz[2 * i + 1], P);
 }
 
 // ---------------------------------------------------------- alignment

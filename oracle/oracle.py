@@ -47,32 +47,67 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def _bind(path: str):
+    """Load an oracle shared library and declare its entry points."""
+    L = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.oc_run.restype = P
+    L.oc_run.argtypes = [P, P, P, P, I, P, I, I]
+    L.oc_seconds.restype = D
+    L.oc_seconds.argtypes = [P]
+    L.oc_threads_used.restype = I
+    L.oc_threads_used.argtypes = [I]
+    L.oc_sizes.argtypes = [P, P, P, P]
+    L.oc_frames.argtypes = [P, P, P, P, P, P, P]
+    L.oc_lists.argtypes = [P, P, P, P, P, P]
+    L.oc_free.argtypes = [P]
+    L.oc_cut_quantities.argtypes = [P, I, P, P, P]
+    L.oc_fit.argtypes = [P, I, P, P, P]
+    L.oc_predict_l3.argtypes = [P, I, P, P, P]
+    L.oc_track4.argtypes = [P, I, P, P, P]
+    L.oc_vertex4.argtypes = [P, I, P, P]
+    L.oc_track_geom.argtypes = [P, I, P, P, P]
+    L.oc_track_point.argtypes = [P, P, I, P, P, P]
+    L.oc_cone_distance.argtypes = [P, I, P, P]
+    L.oc_align_loss_grad.restype = D
+    L.oc_align_loss_grad.argtypes = [P, P, P, P, P, I, P, I, P, P, I, P]
+    L.oc_param_count.restype = I
+    return L
+
+
 def lib():
+    """The oracle library: the in-tree build, or the build named by the
+    environment variable MU3E_ORACLE_LIB (the mutation tests point it at
+    copies of the source with a planted mistake)."""
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB)
-        P, I, D, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
-        L.oc_run.restype = P
-        L.oc_run.argtypes = [P, P, P, P, I, P, I, I]
-        L.oc_seconds.restype = D
-        L.oc_seconds.argtypes = [P]
-        L.oc_threads_used.restype = I
-        L.oc_threads_used.argtypes = [I]
-        L.oc_sizes.argtypes = [P, P, P, P]
-        L.oc_frames.argtypes = [P, P, P, P, P, P, P]
-        L.oc_lists.argtypes = [P, P, P, P, P, P]
-        L.oc_free.argtypes = [P]
-        L.oc_cut_quantities.argtypes = [P, I, P, P, P]
-        L.oc_fit.argtypes = [P, I, P, P, P]
-        L.oc_predict_l3.argtypes = [P, I, P, P, P]
-        L.oc_track4.argtypes = [P, I, P, P, P]
-        L.oc_vertex4.argtypes = [P, I, P, P]
-        L.oc_align_loss_grad.restype = D
-        L.oc_align_loss_grad.argtypes = [P, P, P, P, P, I, P, I, P, P, I, P]
-        L.oc_param_count.restype = I
-        _lib = L
+        alt = os.environ.get("MU3E_ORACLE_LIB")
+        if alt:
+            _lib = _bind(alt)
+        else:
+            build()
+            _lib = _bind(LIB)
     return _lib
+
+
+class use_library:
+    """Context manager: route every call of this module to another build of
+    the oracle source (the mutation tests compile copies with a planted
+    mistake and check that the pins reject them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _bind(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 def pack_params(p: dict) -> np.ndarray:
@@ -197,6 +232,41 @@ def vertex4(h: np.ndarray, params: dict):
     n = len(h)
     out = np.zeros((n, 10))
     lib().oc_vertex4(_ptr(h), n, _ptr(pack_params(params)), _ptr(out))
+    return out
+
+
+TRACK_FIELDS = ("kbar", "rbar", "rt", "cx", "cy", "sms0", "E", "p", "theta1")
+
+
+def track_geom(h: np.ndarray, params: dict):
+    """Vertex-stage quantities of tracks given by four hits; h [n, 4, 3] ->
+    (dict of [n] arrays with TRACK_FIELDS, ok [n])."""
+    h = np.ascontiguousarray(h, np.float64).reshape(-1, 12)
+    n = len(h)
+    out = np.zeros((n, 9))
+    ok = np.zeros(n, np.int32)
+    lib().oc_track_geom(_ptr(h), n, _ptr(pack_params(params)), _ptr(out), _ptr(ok))
+    return {k: out[:, i] for i, k in enumerate(TRACK_FIELDS)}, ok.astype(bool)
+
+
+def track_point(h: np.ndarray, q: np.ndarray, params: dict):
+    """Backward turning angle from the layer-0 hit to the transverse point q,
+    the path length and the position variance there (eq. track-error);
+    h [n, 4, 3], q [n, 2] -> (out [n, 3], ok [n])."""
+    h = np.ascontiguousarray(h, np.float64).reshape(-1, 12)
+    q = np.ascontiguousarray(q, np.float64).reshape(-1, 2)
+    n = len(h)
+    out = np.zeros((n, 3))
+    ok = np.zeros(n, np.int32)
+    lib().oc_track_point(_ptr(h), _ptr(q), n, _ptr(pack_params(params)), _ptr(out), _ptr(ok))
+    return out, ok.astype(bool)
+
+
+def cone_distance(rz: np.ndarray, params: dict):
+    """Distance of (rho, z) points [n, 2] to the double-cone target surface."""
+    rz = np.ascontiguousarray(rz, np.float64).reshape(-1, 2)
+    out = np.zeros(len(rz))
+    lib().oc_cone_distance(_ptr(rz), len(rz), _ptr(pack_params(params)), _ptr(out))
     return out
 
 

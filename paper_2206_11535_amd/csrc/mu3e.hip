@@ -1856,7 +1856,7 @@ mu3e_status mu3e_select_frames(const mu3e_hits_t* hits, const mu3e_params_t* par
 
 mu3e_status mu3e_fit_triplets(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const mu3e_params_t* params,
                               float* out, hipStream_t stream) {
-  if (!hits || n < 0 || !params || (n > 0 && (!trip || !out || !hits->x || !hits->y || !hits->z)))
+  if (!hits || hits->n_hits < 0 || n < 0 || !params || (n > 0 && (!trip || !out || !hits->x || !hits->y || !hits->z)))
     return MU3E_ERR_INVALID_ARG;
   Consts C;
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
@@ -1876,7 +1876,8 @@ size_t mu3e_vertex_workspace_size(int32_t n_tracks) {
 mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, const mu3e_params_t* params,
                         uint32_t* frame_flags, int32_t* frame_combos, float* frame_vertex, void* workspace,
                         size_t workspace_bytes, hipStream_t stream) {
-  if (!hits || !tracks || !params || tracks->n_frames < 0 || tracks->n_tracks < 0) return MU3E_ERR_INVALID_ARG;
+  if (!hits || hits->n_hits < 0 || !tracks || !params || tracks->n_frames < 0 || tracks->n_tracks < 0)
+    return MU3E_ERR_INVALID_ARG;
   Consts C;
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
   const int F = tracks->n_frames, n = tracks->n_tracks;
@@ -1902,7 +1903,7 @@ mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, co
 mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t* hits, const int32_t* trip, int32_t n,
                                        const mu3e_params_t* params, const float* grad_chi2, float* grad_xyz,
                                        hipStream_t stream) {
-  if (!hits || n < 0 || !params ||
+  if (!hits || hits->n_hits < 0 || n < 0 || !params ||
       (n > 0 && (!trip || !grad_chi2 || !grad_xyz || !hits->x || !hits->y || !hits->z)))
     return MU3E_ERR_INVALID_ARG;
   Consts C;
@@ -1922,7 +1923,7 @@ size_t mu3e_align_workspace_size(int32_t n_sensors) {
 
 static bool align_args_ok(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const float* theta,
                           int32_t n_sensors) {
-  return hits && n >= 0 && n_sensors > 0 &&
+  return hits && hits->n_hits >= 0 && n >= 0 && n_sensors > 0 &&
          (n == 0 || (trip && theta && hits->x && hits->y && hits->z && hits->sensor));
 }
 

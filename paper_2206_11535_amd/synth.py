@@ -245,13 +245,15 @@ def quantise(phi_true, z_true, R):
     return R * np.cos(uq / R), R * np.sin(uq / R), zq
 
 
-def propagate(rng, pos, mom, charge, ms=True, quant=True, accept=True):
+def propagate(rng, pos, mom, charge, ms=True, quant=True, accept=True, ms_layers=(0, 1, 2, 3)):
     """Propagate particles through the four layers.
 
     pos, mom: [n, 3]; charge: [n] (+1/-1).  Returns hit arrays
     (pid, layer, x, y, z) for the recorded crossings.  ms / quant / accept
     switch multiple scattering, pixel quantisation and the z acceptance off
-    (noiseless helices for closed-form checks).
+    (noiseless helices for closed-form checks); ms_layers restricts the
+    scattering to the listed layers (the angles are drawn for every layer
+    either way, so the draw order does not change).
     """
     n = len(charge)
     pos = pos.copy()
@@ -302,7 +304,7 @@ def propagate(rng, pos, mom, charge, ms=True, quant=True, accept=True):
             else:
                 hx, hy, hz = pos[idx, 0].copy(), pos[idx, 1].copy(), pos[idx, 2].copy()
             rec.append((idx, np.full(len(idx), layer), hx, hy, hz))
-            if not ms:
+            if not ms or layer not in ms_layers:
                 continue
             # multiple scattering in the sensor material
             p = np.linalg.norm(mom[idx], axis=1)

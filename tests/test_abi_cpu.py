@@ -100,6 +100,20 @@ def test_host_validation(L):
     assert plan.value is None
     # timed plan run without a plan or events
     assert L.mu3e_plan_run_timed(None, None, None) == -1
+    # a negative hit count is refused by every entry point that reads hits,
+    # before any launch (with n_hits < 0 an index check (unsigned)g < n_hits
+    # in the kernels would otherwise accept negative indices)
+    hn = lib.Hits(16, 32, 48, None, 112, 64, 5, -1)
+    sens = L.mu3e_align_workspace_size(8)
+    assert L.mu3e_select_frames(ctypes.byref(hn), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10, None, None) == -1
+    assert L.mu3e_fit_triplets(ctypes.byref(hn), 1, 5, ctypes.byref(p), 1, None) == -1
+    assert L.mu3e_fit_triplets_backward(ctypes.byref(hn), 1, 5, ctypes.byref(p), 1, 1, None) == -1
+    assert L.mu3e_vertex(ctypes.byref(hn), ctypes.byref(lib.Tracks(80, 96, 4, 10)), ctypes.byref(p), 1, 1, 1, 1,
+                         1 << 20, None) == -1
+    assert L.mu3e_align_chi2(ctypes.byref(hn), 1, 5, 1, 8, ctypes.byref(p), 1, None) == -1
+    assert L.mu3e_align_backward(ctypes.byref(hn), 1, 5, 1, 8, ctypes.byref(p), 1, 1, 1, sens, None) == -1
+    assert L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(hn), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10,
+                              None) == -1
 
 
 def test_binding_fails_loudly_without_library():
