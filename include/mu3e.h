@@ -179,6 +179,30 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t *hits, const mu3e_params_
                                      mu3e_debug_t *dbg, hipStream_t stream,
                                      hipEvent_t *stage_events);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mu3e_select_frames with its workspace taken from a library-owned static
+ * device array of MU3E_STATIC_SCRATCH_BYTES (64 MiB; one copy per GPU the
+ * library runs on, held until the process ends), so the call allocates
+ * nothing.  The caller still owns the hits and the outputs.  A request whose
+ * workspace (mu3e_select_workspace_size of n_frames, triplet_capacity,
+ * track_capacity) exceeds the array returns MU3E_ERR_CAPACITY before
+ * anything is launched; e.g. 100,000 nominal-rate frames fit with
+ * triplet_capacity 2^21 and track_capacity 65536.  The first call on a device
+ * resolves the array's address there (with that device current).  Every
+ * call on a GPU uses that GPU's one array: calls that overlap in time on one
+ * GPU (on different streams, or from different threads) race and give
+ * undefined results, so serialise them (e.g. one stream).  The array keeps
+ * the last call's contents; the counters that must start at zero are cleared
+ * by the call's first kernel.  dbg (nullable) then points into the array and
+ * stays valid until the next call on that GPU. */
+#define MU3E_STATIC_SCRATCH_BYTES (64u << 20)
+mu3e_status mu3e_select_frames_static(const mu3e_hits_t *hits, const mu3e_params_t *params,
+                                      uint32_t *frame_flags, int32_t *frame_counts,
+                                      float *frame_vertex, int32_t triplet_capacity,
+                                      int32_t track_capacity, mu3e_debug_t *dbg,
+                                      hipStream_t stream);
+
 /* Single triplet fit (Section IV-B) of n explicit triplets of global hit
  * indices trip[n][3] (layer order 0,1,2 or 1,2,3).  out[n][8]: kappa,
  * sigma^2_kappa, chi2_min, R*, sigma^2_R, signed circumradius, theta_C1,

@@ -37,7 +37,15 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+
+// Workspace of mu3e_select_frames_static: one copy per device, held by each
+// device the library runs on until the process ends.  Host code never passes
+// this name to a kernel or a copy (on the host it is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress returns for the current
+// device.
+static __device__ __align__(256) unsigned char scratch[MU3E_STATIC_SCRATCH_BYTES];
 
 using namespace mu3e;
 
@@ -1804,10 +1812,15 @@ size_t mu3e_select_workspace_size(int32_t n_frames, int32_t triplet_capacity, in
   return layout(n_frames, triplet_capacity, track_capacity).total;
 }
 
-mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
-                                     int32_t* frame_counts, float* frame_vertex, void* workspace,
-                                     size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
-                                     mu3e_debug_t* dbg, hipStream_t stream, hipEvent_t* ev) {
+}  // extern "C"
+
+namespace {
+
+// The plain-form sequence of mu3e_select_frames on a given workspace.
+mu3e_status select_impl(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
+                        int32_t* frame_counts, float* frame_vertex, void* workspace, size_t workspace_bytes,
+                        int32_t triplet_capacity, int32_t track_capacity, mu3e_debug_t* dbg, hipStream_t stream,
+                        hipEvent_t* ev) {
   if (!hits_ok(hits) || !params || triplet_capacity < 0 || triplet_capacity > kMaxTripletCapacity ||
       track_capacity < 0)
     return MU3E_ERR_INVALID_ARG;
@@ -1846,13 +1859,61 @@ mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
+// Device address of `scratch` on each device, resolved on the first call of
+// mu3e_select_frames_static on that device (with the device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+mu3e_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MU3E_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return MU3E_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MU3E_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MU3E_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mu3e_status mu3e_select_frames_timed(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
+                                     int32_t* frame_counts, float* frame_vertex, void* workspace,
+                                     size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
+                                     mu3e_debug_t* dbg, hipStream_t stream, hipEvent_t* ev) {
+  return select_impl(hits, params, frame_flags, frame_counts, frame_vertex, workspace, workspace_bytes,
+                     triplet_capacity, track_capacity, dbg, stream, ev);
+}
+
 mu3e_status mu3e_select_frames(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
                                int32_t* frame_counts, float* frame_vertex, void* workspace,
                                size_t workspace_bytes, int32_t triplet_capacity, int32_t track_capacity,
                                mu3e_debug_t* dbg, hipStream_t stream) {
-  return mu3e_select_frames_timed(hits, params, frame_flags, frame_counts, frame_vertex, workspace,
-                                  workspace_bytes, triplet_capacity, track_capacity, dbg, stream, nullptr);
+  return select_impl(hits, params, frame_flags, frame_counts, frame_vertex, workspace, workspace_bytes,
+                     triplet_capacity, track_capacity, dbg, stream, nullptr);
 }
+
+mu3e_status mu3e_select_frames_static(const mu3e_hits_t* hits, const mu3e_params_t* params, uint32_t* frame_flags,
+                                      int32_t* frame_counts, float* frame_vertex, int32_t triplet_capacity,
+                                      int32_t track_capacity, mu3e_debug_t* dbg, hipStream_t stream) {
+  // sizes first (no device call): a request beyond the static array is refused
+  if (!hits || hits->n_frames < 0 || triplet_capacity < 0 || triplet_capacity > kMaxTripletCapacity ||
+      track_capacity < 0)
+    return MU3E_ERR_INVALID_ARG;
+  if (layout(hits->n_frames, triplet_capacity, track_capacity).total > sizeof(scratch)) return MU3E_ERR_CAPACITY;
+  void* ws = nullptr;
+  const mu3e_status st = scratch_of_current_device(&ws);
+  if (st != MU3E_OK) return st;
+  return select_impl(hits, params, frame_flags, frame_counts, frame_vertex, ws, sizeof(scratch), triplet_capacity,
+                     track_capacity, dbg, stream, nullptr);
+}
+
 
 mu3e_status mu3e_fit_triplets(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const mu3e_params_t* params,
                               float* out, hipStream_t stream) {

@@ -106,6 +106,9 @@ def load(path: str = LIB_PATH):
     L.mu3e_select_frames_timed.restype = ctypes.c_int
     L.mu3e_select_frames_timed.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Params), P, P, P, P, Z, I, I,
                                            ctypes.POINTER(Debug), P, P]
+    L.mu3e_select_frames_static.restype = ctypes.c_int
+    L.mu3e_select_frames_static.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Params), P, P, P, I, I,
+                                            ctypes.POINTER(Debug), P]
     L.mu3e_fit_triplets.restype = ctypes.c_int
     L.mu3e_fit_triplets.argtypes = [ctypes.POINTER(Hits), P, I, ctypes.POINTER(Params), P, P]
     L.mu3e_fit_triplets_backward.restype = ctypes.c_int
@@ -323,6 +326,28 @@ def select_frames(hits: DeviceHits, params: dict, stream=None, **kw):
     s = Selector(hits.n_frames, params, **kw)
     s.run(hits, stream)
     return s
+
+
+def select_frames_static(hits: DeviceHits, params: dict, triplet_capacity: int, track_capacity: int,
+                         flags=None, counts=None, vertex=None, stream=None):
+    """mu3e_select_frames_static: the selection with the library's static
+    per-GPU workspace (the call itself allocates nothing; outputs are
+    allocated here unless given).  Returns (flags, counts, vertex) tensors."""
+    import torch
+    F = hits.n_frames
+    dev = hits.x.device
+    flags = torch.empty(max(F, 1), dtype=torch.int32, device=dev) if flags is None else flags
+    counts = torch.empty((max(F, 1), 3), dtype=torch.int32, device=dev) if counts is None else counts
+    vertex = torch.empty((max(F, 1), 4), dtype=torch.float32, device=dev) if vertex is None else vertex
+    if flags.numel() < F or counts.numel() < 3 * F or vertex.numel() < 4 * F:
+        raise ValueError("output tensors too small for the frames")
+    hs = hits.struct()
+    dbg = Debug()
+    _check(load().mu3e_select_frames_static(ctypes.byref(hs), ctypes.byref(make_params(params)), _ptr(flags),
+                                            _ptr(counts), _ptr(vertex), int(triplet_capacity),
+                                            int(track_capacity), ctypes.byref(dbg), _stream(stream)),
+           "mu3e_select_frames_static")
+    return flags, counts, vertex
 
 
 def fit_triplets(hits: DeviceHits, trip, params: dict, stream=None):

@@ -90,6 +90,13 @@ def test_host_validation(L):
     assert L.mu3e_select_workspace_size(10, (1 << 30) + 1, 10) == 0
     assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, (1 << 30) + 1, 10, None,
                                 None) == -1
+    # the static-workspace entry: a request beyond the library's array, and
+    # negative sizes, are refused before any device call
+    assert L.mu3e_select_frames_static(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1 << 30, 1 << 20, None,
+                                       None) == -3
+    assert L.mu3e_select_frames_static(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, -1, 10, None, None) == -1
+    assert L.mu3e_select_frames_static(ctypes.byref(h2), ctypes.byref(p), 1, 1, 1, 10, 10, None, None) == -1
+    assert L.mu3e_select_frames_static(None, ctypes.byref(p), 1, 1, 1, 10, 10, None, None) == -1
     # plan: null out pointer, invalid steal share (checked before any device call)
     t = lib.Tuning(8, 4, 0, 101)
     assert L.mu3e_plan_create(None, ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10,
