@@ -29,9 +29,12 @@
  * and nothing is launched.  Conditions only known on the device (a candidate
  * list in the workspace filled up) are reported in the workspace's status
  * word, readable after the stream has been synchronised (mu3e_debug_t).
- * Exceeding a *method* cap (max_triplets, max_tracks, max_combos,
- * max_layer_hits) is not an error: the frame's overflow flag is set and the
- * frame is kept, as the paper's implementation marks such frames for storage.
+ * Exceeding a *method* cap (max_triplets, max_tracks, max_combos) is not an
+ * error: the frame's overflow flag is set and the frame is kept, as the
+ * paper's implementation marks such frames for storage.  max_layer_hits is a
+ * capacity of this implementation, not of the method (frame-local hit
+ * indices are packed in 10 bits): a frame above it is kept unprocessed, the
+ * same fail-safe.
  */
 #ifndef MU3E_H
 #define MU3E_H
@@ -59,11 +62,13 @@ enum {
   MU3E_TRACK_OVF = 4u,     /* more than max_tracks tracks passed chi2 < max    */
   MU3E_COMBO_OVF = 8u,     /* more than max_combos e+e+e- triples passed dE    */
   MU3E_VERTEX = 16u,       /* a signal-like vertex was found                   */
-  MU3E_HITS_OVF = 32u      /* a layer holds more than max_layer_hits hits      */
+  MU3E_HITS_OVF = 32u      /* a layer holds more than max_layer_hits hits
+                              (a capacity flag, see above)                     */
 };
 
-/* Largest per-layer hit count the kernels stage in LDS. */
-#define MU3E_MAX_LAYER_HITS 128
+/* Largest per-layer hit count the kernels process.  Layers are staged in LDS
+ * in tiles of 64 or 128 hits; a frame with a larger layer runs tile by tile. */
+#define MU3E_MAX_LAYER_HITS 1023
 
 /* Hits of a batch of frames (device pointers).  layer and sensor may be NULL
  * for calls that do not need them. */
@@ -92,7 +97,7 @@ typedef struct {
   int32_t max_triplets;      /* cap of the selected-triplet list (768)            */
   int32_t max_tracks;        /* cap of the track list                             */
   int32_t max_combos;        /* cap of the energy-passing e+e+e- triple list      */
-  int32_t max_layer_hits;    /* <= MU3E_MAX_LAYER_HITS                            */
+  int32_t max_layer_hits;    /* capacity, <= MU3E_MAX_LAYER_HITS                  */
   float de_max;              /* |sum E - m_mu| <= de_max                          */
   float r_target;            /* target radius (19)                                */
   float target_tol;          /* intersections within r_target + target_tol        */
@@ -121,7 +126,7 @@ typedef struct {
  *                first min(counters[7], triplet_capacity) / chunk size rows,
  *                and chunk c starts at c * chunk size
  *   triplets     [triplet_capacity][2]: frame, packed frame-local
- *                indices i0 | i1 << 8 | i2 << 16 (hit = layer_offsets[4f+l] + il)
+ *                indices i0 | i1 << 10 | i2 << 20 (hit = layer_offsets[4f+l] + il)
  *   tracks       [triplet_capacity][4], parallel to triplets: code (1 the
  *                triplet starts an accepted track, 0 not, 2 undecided: only
  *                when the re-evaluation list was full), frame-local
@@ -250,6 +255,20 @@ mu3e_status mu3e_vertex(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
                         int32_t *frame_combos, float *frame_vertex, void *workspace,
                         size_t workspace_bytes, hipStream_t stream);
 
+/* mu3e_vertex that also lists the e+e+e- triples passing the energy test
+ * (the debug view of Alg. 4's preliminary check): rows triples[r][4] =
+ * {frame, track a, track b, track c} (global track indices into
+ * tracks->hit; a and b the positive tracks, c the negative one), in no
+ * particular order.  *n_triples (a device int32 the caller zeroes before the
+ * call) receives the number of passing triples; rows beyond
+ * triple_capacity are not written.  triples may be NULL (then the call is
+ * mu3e_vertex). */
+mu3e_status mu3e_vertex_debug(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks,
+                              const mu3e_params_t *params, uint32_t *frame_flags,
+                              int32_t *frame_combos, float *frame_vertex, void *workspace,
+                              size_t workspace_bytes, int32_t *triples, int32_t triple_capacity,
+                              int32_t *n_triples, hipStream_t stream);
+
 /* ---- Batched form ------------------------------------------------------
  * A plan captures the whole selection of one batch of frames into a HIP
  * graph around one persistent kernel: waves take the frames of the batch
@@ -274,29 +293,60 @@ typedef struct {
   int32_t steal_percent;      /* 0..100: share of the frames (the tail of the
                                  batch) taken by work stealing; the rest is
                                  dealt cyclically                              */
+  int32_t tile_hits;          /* LDS tile of the cuts: hits per layer staged at
+                                 once, 64 or 128 (0: 128); a frame with a
+                                 layer above it runs tile by tile.  Smaller
+                                 tiles take half the LDS, so more waves fit
+                                 on a compute unit                             */
+  int32_t sub_batches;        /* 1..4 (0: 1): the batch is split into this many
+                                 contiguous ranges of frames, each with its own
+                                 part of the workspace; the cuts of one run
+                                 while the fits and vertex stage of the one
+                                 before run on another stream                  */
 } mu3e_tuning_t;
 
-/* Workspace as mu3e_select_workspace_size.  tuning may be NULL.  Allocates
- * the plan object and the graph (host and driver memory). */
+/* Workspace bytes of a plan over n_frames frames with the given capacities
+ * split over sub_batches (0 or 1: the same as mu3e_select_workspace_size).
+ * Returns 0 for invalid sizes. */
+size_t mu3e_plan_workspace_size(int32_t n_frames, int32_t triplet_capacity,
+                                int32_t track_capacity, int32_t sub_batches);
+
+/* Workspace as mu3e_plan_workspace_size (the capacities are split evenly
+ * over the sub-batches).  tuning may be NULL.  Allocates the plan object,
+ * two graphs per sub-batch, and a stream and two events per sub-batch after
+ * the first (host and driver memory; the streams have the default
+ * priority). */
 mu3e_status mu3e_plan_create(mu3e_plan_t **plan, const mu3e_hits_t *hits,
                              const mu3e_params_t *params, uint32_t *frame_flags,
                              int32_t *frame_counts, float *frame_vertex, void *workspace,
                              size_t workspace_bytes, int32_t triplet_capacity,
                              int32_t track_capacity, const mu3e_tuning_t *tuning);
 
-/* One graph launch on the stream (asynchronous; no allocation). */
+/* One run of the batch (asynchronous; no allocation): sub-batch 0 on the
+ * given stream, sub-batch j > 0 on the plan's stream j, each as two graph
+ * launches (cuts; fits and vertex stage); the cuts of sub-batch j wait for
+ * those of sub-batch j - 1, and the given stream waits for every
+ * sub-batch, so work queued on it afterwards sees the whole batch done. */
 mu3e_status mu3e_plan_run(mu3e_plan_t *plan, hipStream_t stream);
 
-/* The same kernel sequence as mu3e_plan_run, launched directly on the stream
- * (no graph) with events[0..3] (caller-created, timing enabled) recorded
- * before and after the persistent kernel, after the fit kernel and after the
- * last kernel, so that kernel durations can be measured on the stream they
- * run on.  Identical outputs. */
+/* The same kernel sequence as mu3e_plan_run, launched directly on the given
+ * stream (no graph; the sub-batches one after another) with four events per
+ * sub-batch, events[4j .. 4j+3] (caller-created, timing enabled, 4 *
+ * sub_batches in all), recorded before and after its persistent kernel,
+ * after its fit kernel and after its last kernel, so that kernel durations
+ * can be measured on the stream they run on.  Identical outputs. */
 mu3e_status mu3e_plan_run_timed(mu3e_plan_t *plan, hipStream_t stream, hipEvent_t *events);
 
-/* The plan's debug view (as mu3e_select_frames fills it) and the tuning in
- * effect; either pointer may be NULL. */
+/* The debug view of sub-batch 0 (as mu3e_select_frames fills it) and the
+ * tuning in effect; either pointer may be NULL. */
 mu3e_status mu3e_plan_info(const mu3e_plan_t *plan, mu3e_debug_t *dbg, mu3e_tuning_t *tuning);
+
+/* The debug view of sub-batch `part` (0 <= part < sub_batches in effect) and
+ * its frames [first_frame, first_frame + n_frames) of the batch; the frame
+ * numbers in its triplet list are relative to first_frame.  Any output
+ * pointer may be NULL. */
+mu3e_status mu3e_plan_part_info(const mu3e_plan_t *plan, int32_t part, mu3e_debug_t *dbg,
+                                int32_t *first_frame, int32_t *n_frames);
 
 void mu3e_plan_destroy(mu3e_plan_t *plan);
 

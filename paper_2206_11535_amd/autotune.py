@@ -1,12 +1,17 @@
-"""Autotuner of the batched form: persistent waves per compute unit, the
-share of frames taken by work stealing, frames per claim, and whether the
-persistent waves also fit.
+"""Autotuner of the batched form: persistent waves per compute unit, the LDS
+tile of the cuts (hits per layer staged at once), whether the persistent
+waves also fit, the share of frames taken by work stealing, the frames per
+claim, and the number of sub-batches a batch is split into (the cuts of one
+overlapping the fits and vertex stage of the one before).
 
-Each candidate plan runs the given workload (already resident on the GPU);
-its mean step time over event-timed repeats is measured and the fastest
-shape is cached in tuning_cache.json, keyed by GPU architecture, ROCm
-version, a hash of the kernel sources and the workload class (frames and
-mean hits per frame, rounded).
+The search runs in three stages on the given workload (already resident on
+the GPU): first the purely cyclic schedule over every wave count, tile size
+and fusion choice, then stealing tails around the best of those, then the
+sub-batch count at the best shape.  Each
+candidate plan's mean step time over event-timed repeats is measured and the
+fastest shape is cached in tuning_cache.json, keyed by GPU architecture,
+ROCm version, a hash of the kernel sources and the workload class (frames
+and mean hits per frame, rounded).
 """
 from __future__ import annotations
 
@@ -14,25 +19,40 @@ import hashlib
 import json
 import os
 
-import numpy as np
-
 PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(PKG, "tuning_cache.json")
 
-WAVES_PER_CU = (4, 8, 12, 16, 20, 24, 32)
+FIELDS = ("waves_per_cu", "frames_per_claim", "fuse_fits", "steal_percent", "tile_hits", "sub_batches")
+WAVES_PER_CU = (4, 8, 12, 16, 20, 24, 28, 32)
+TILE_HITS = (64, 128)
 FUSE_FITS = (0, 1)
 STEAL_PERCENT = (12, 25, 50)
 STEAL_WAVES_PER_CU = (8, 12, 16)
-FRAMES_PER_CLAIM = (4, 8, 16, 32)
+FRAMES_PER_CLAIM = (1, 4, 8, 16)
+SUB_BATCHES = (1, 2, 3, 4)
 
 
-def candidates():
-    """(waves_per_cu, frames_per_claim, fuse_fits, steal_percent) shapes: the
-    purely cyclic schedule at every wave count, and stealing tails."""
-    out = [(w, 0, u, 0) for u in FUSE_FITS for w in WAVES_PER_CU]
-    out += [(w, c, u, st) for u in FUSE_FITS for st in STEAL_PERCENT for w in STEAL_WAVES_PER_CU
-            for c in FRAMES_PER_CLAIM]
-    return out
+def cyclic_candidates():
+    """Stage 1: the purely cyclic schedule at every wave count, tile size
+    and fusion choice (frames_per_claim unused)."""
+    return [(w, 0, u, 0, t, 1) for t in TILE_HITS for u in FUSE_FITS for w in WAVES_PER_CU]
+
+
+def steal_candidates(best):
+    """Stage 2: stealing tails at the best stage-1 tile and fusion choice,
+    at its wave count and at STEAL_WAVES_PER_CU."""
+    w0, _, u, _, t, _ = best
+    waves = sorted(set(STEAL_WAVES_PER_CU) | {w0})
+    return [(w, c, u, st, t, 1) for st in STEAL_PERCENT for w in waves for c in FRAMES_PER_CLAIM]
+
+
+def split_candidates(best):
+    """Stage 3: the best shape so far split into more sub-batches."""
+    return [(*best[:5], n) for n in SUB_BATCHES if n > 1]
+
+
+def as_kwargs(shape) -> dict:
+    return dict(zip(FIELDS, (int(v) for v in shape)))
 
 
 def source_tag() -> str:
@@ -74,8 +94,8 @@ def time_plan(sel, reps: int = 5, warmup: int = 2) -> float:
 
 
 def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: int = 5,
-         candidates_=None, use_cache: bool = True, verbose: bool = False):
-    """Return ((waves_per_cu, frames_per_claim, fuse_fits, steal_percent), ms, table)."""
+         use_cache: bool = True, verbose: bool = False):
+    """Return (shape, ms, table); shape is a tuple in the order of FIELDS."""
     import torch
     from . import lib
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
@@ -83,29 +103,34 @@ def tune(hits, params: dict, triplet_capacity=None, track_capacity=None, reps: i
     cache = load_cache()
     if use_cache and key in cache:
         e = cache[key]
-        return (e["waves_per_cu"], e["frames_per_claim"], e["fuse_fits"], e["steal_percent"]), e["ms"], None
+        return tuple(e[k] for k in FIELDS), e["ms"], None
     table = []
     seen = set()
-    for w, c, u, st in candidates_ or candidates():
-        sel = lib.BatchedSelector(hits, params, triplet_capacity, track_capacity, waves_per_cu=w,
-                                  frames_per_claim=c, fuse_fits=u, steal_percent=st)
-        if sel.effective in seen:          # capped by occupancy: same shape as before
+
+    def measure(cands):
+        for shape in cands:
+            sel = lib.BatchedSelector(hits, params, triplet_capacity, track_capacity, **as_kwargs(shape))
+            eff = sel.effective
+            if eff in seen:          # capped by occupancy: a shape measured before
+                del sel
+                continue
+            seen.add(eff)
+            ms = time_plan(sel, reps)
+            table.append((*eff, ms))
+            if verbose:
+                print("  " + " ".join(f"{k} {v}" for k, v in zip(FIELDS, eff)) + f": {ms:.4f} ms", flush=True)
             del sel
-            continue
-        seen.add(sel.effective)
-        ms = time_plan(sel, reps)
-        table.append((*sel.effective, ms))
-        if verbose:
-            e = sel.effective
-            print(f"  waves/CU {e[0]:3d} frames/claim {e[1]:3d} fused {e[2]} steal {e[3]:3d}%: {ms:.4f} ms",
-                  flush=True)
-        del sel
-    best = min(table, key=lambda r: r[4])
+
+    measure(cyclic_candidates())
+    best1 = min(table, key=lambda r: r[-1])
+    measure(steal_candidates(best1[:-1]))
+    best2 = min(table, key=lambda r: r[-1])
+    measure(split_candidates(best2[:-1]))
+    best = min(table, key=lambda r: r[-1])
     # entries measured on other kernel sources are stale: drop them
     tag = f"|src{source_tag()}|"
     cache = {k: v for k, v in cache.items() if "|src" not in k or tag in k}
-    cache[key] = {"waves_per_cu": best[0], "frames_per_claim": best[1], "fuse_fits": best[2],
-                  "steal_percent": best[3], "ms": best[4]}
+    cache[key] = {**as_kwargs(best[:-1]), "ms": best[-1]}
     with open(CACHE, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
-    return tuple(best[:4]), best[4], table
+    return tuple(best[:-1]), best[-1], table

@@ -261,15 +261,35 @@ __device__ inline bool cos_cut_wave(bool act, float x0, float y0, float x1, floa
 }
 
 // =================================================================== k_cuts
+constexpr int kPlainTile = 128;      // LDS tile (hits per layer) of the plain form's cuts
 constexpr int kJoinQueue = 2 * 64;   // combinations passing Delta lambda awaiting r_tc (< 2 waves)
 constexpr uint32_t kDlAmbiguous = 1u << 24;     // queued combination whose Delta lambda float32 cannot decide
 constexpr uint32_t kPhi12Ambiguous = 1u << 25;  // queued pair / combination whose cos Phi12 float32 cannot decide
 
+// Frame-local hit indices of a triplet-list entry: i0 | i1 << 10 | i2 << 20,
+// so that a layer may hold up to 1023 hits (larger layers are tiled through
+// LDS by the cuts).
+constexpr int kIdxBits = 10;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+static_assert(kMaxTiledLayerHits == (int)kIdxMask, "index packing and layer capacity disagree");
+
+__device__ inline uint32_t pack_local(int i0, int i1, int i2) {
+  return (uint32_t)i0 | ((uint32_t)i1 << kIdxBits) | ((uint32_t)i2 << (2 * kIdxBits));
+}
+
+// LDS of the cuts of one wave for tiles of at most TT (64 or 128) hits per
+// layer: the tile's layer-0..2 hits, per layer-1 hit a mask of its layer-0
+// partners passing Phi01 (TT / 64 words), the queue of (h1, h2) pairs
+// passing Phi12 and the queue of combinations passing Delta lambda that
+// await the r_tc test.  A frame whose layers fit one tile is staged once; a
+// larger one runs tile by tile.
+template <int TT>
 struct CutLds {
-  float sx[3 * kMaxLayerHits], sy[3 * kMaxLayerHits], sz[3 * kMaxLayerHits];
-  unsigned long long sm01[2 * kMaxLayerHits];
-  uint32_t spend[2 * kWave];
-  uint32_t sjoin[kJoinQueue];   // packed i1 | i2 << 8 | i0 << 16, kDlAmbiguous, kPhi12Ambiguous
+  static constexpr int W = TT / 64;
+  float sx[3 * TT], sy[3 * TT], sz[3 * TT];
+  unsigned long long sm01[W * TT];
+  uint32_t spend[2 * kWave];    // packed tile-local i1 | i2 << 8, kPhi12Ambiguous
+  uint32_t sjoin[kJoinQueue];   // packed tile-local i1 | i2 << 8 | i0 << 16, kDlAmbiguous, kPhi12Ambiguous
 };
 
 // ------------------------------------------------------------ frame loads
@@ -300,21 +320,223 @@ __device__ inline void load_hits(FrameRegs& R, const float* __restrict__ X, cons
   }
 }
 
+// Phi01 of one tile (Alg. 2): over all (i0, i1) pairs of the staged layer-0
+// and layer-1 tiles (n0, n1 hits), the bit of i0 is set in i1's partner mask.
+template <int TT>
+__device__ __attribute__((always_inline)) inline void phi01_tile(int n0, int n1, const Consts& C, CutLds<TT>& L) {
+  constexpr int W = CutLds<TT>::W;
+  const int lane = threadIdx.x;
+  const int n01 = n0 * n1;
+  // hardware reciprocal (about 1 ulp): (p + 0.5) / n0 stays at least
+  // 0.5 / n0 >= 1/256 from an integer, far above its rounding error, so the
+  // truncation below is exact
+  const float r0 = __builtin_amdgcn_rcpf((float)n0);
+  for (int base = 0; base < n01; base += kWave) {
+    const int p = base + lane;
+    const bool act = p < n01;
+    const int i1 = act ? (int)(((float)p + 0.5f) * r0) : 0;   // exact for p < 2^14
+    const int i0 = act ? p - i1 * n0 : 0;
+    if (cos_cut_wave(act, L.sx[i0], L.sy[i0], L.sx[TT + i1], L.sy[TT + i1], C.invRR01, C.c01_lo, C.c01_hi, C.R[0],
+                     C.R[1]))
+      atomicOr(&L.sm01[W * i1 + (W == 2 ? (i0 >> 6) : 0)], 1ull << (i0 & 63));
+  }
+}
+
+// Phi12, the join and r_tc of one tile whose Phi01 masks are built: (h1, h2)
+// pairs passing Phi12 are streamed through an LDS queue and each full wave of
+// pairs is joined against its Phi01 partners (Delta lambda tested as they
+// are expanded), the combinations passing it are queued and tested on r_tc
+// a full wave at a time.  Survivors are ballot-compacted into the wave's
+// chunks of the triplet list with their frame-local indices (tile-local
+// index + tile start a0, a1, a2).  Returns the number of survivors.
+template <int TT>
+__device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, int n2, int a0, int a1, int a2,
+                                                               const Consts& C, CutLds<TT>& L, const TripList& T,
+                                                               Cursor& cur, int& done,
+                                                               int32_t* __restrict__ counters) {
+  constexpr int W = CutLds<TT>::W;
+  const int lane = threadIdx.x;
+  int total = 0;
+  // r_tc test of the first m (<= kWave) queued combinations, one per lane
+  // (with the float64 Phi12 and Delta lambda decisions of those marked
+  // ambiguous); survivors are ballot-compacted into the wave's chunks.
+  auto test = [&](int m) {
+    const bool act = lane < m;
+    const uint32_t c3 = act ? L.sjoin[lane] : 0u;
+    const int j1 = c3 & 0xff, j2 = (c3 >> 8) & 0xff, j0 = (c3 >> 16) & 0xff;
+    const float x0 = L.sx[j0], y0 = L.sy[j0];
+    const float x1 = L.sx[TT + j1], y1 = L.sy[TT + j1];
+    const float x2 = L.sx[2 * TT + j2], y2 = L.sy[2 * TT + j2];
+    const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
+    bool rpass = vr.pass;
+    const bool damb = act && (c3 & kDlAmbiguous), pamb = act && (c3 & kPhi12Ambiguous);
+    if (ballot(damb || pamb || (act && vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
+      if ((pamb && !cos_refine(x1, y1, x2, y2, C.c12_lo, C.c12_hi, C.R[1], C.R[2])) ||
+          (damb && !dl_refine(L.sz[j0], L.sz[TT + j1], L.sz[2 * TT + j2], C.R[0], C.R[1], C.R[2], C.dl_lo,
+                              C.dl_hi)))
+        rpass = false;
+      else if (act && vr.amb)
+        rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
+    }
+    const bool pass = act && rpass;
+    const unsigned long long bm = ballot(pass);
+    const int c = __popcll(bm);
+    if (c > 0) {
+      if (cur.id != kListFull && (cur.id < 0 || cur.used + c > T.chunk)) {
+        cursor_close(cur, done, T);
+        cursor_open(cur, T, counters);
+        done = 0;
+      }
+      if (cur.id >= 0) {
+        if (pass) {
+          const int slot = cur.id * T.chunk + cur.used + rank_below(bm);
+          *reinterpret_cast<int2*>(T.trips + 2 * slot) = make_int2(f, (int32_t)pack_local(a0 + j0, a1 + j1, a2 + j2));
+        }
+        cur.used += c;
+      }
+    }
+    total += c;
+  };
+  // Join of the k pending (h1, h2) pairs with their Phi01 partners: each
+  // lane visits its pair's partners one per round and tests Delta lambda
+  // (which needs only z); the passing combinations are ballot-compacted
+  // into an LDS queue, and each full wave of them is tested on r_tc, so
+  // that the costly test runs on full waves of the few survivors.
+  int nq = 0;   // queued combinations, < kWave between rounds
+  auto join = [&](int k) {
+    const bool have = lane < k;
+    const uint32_t e = have ? L.spend[lane] : 0u;
+    const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
+    unsigned long long w0 = have ? L.sm01[W * i1] : 0ull;
+    unsigned long long w1 = (W == 2 && have) ? L.sm01[W * i1 + 1] : 0ull;
+    const float z1 = L.sz[TT + i1], z2 = L.sz[2 * TT + i2];
+    const float t12 = (z2 - z1) * C.inv12;
+    while (ballot((w0 | w1) != 0ull) != 0ull) {
+      // next partner, taken without a branch: the lowest set bit of the
+      // first non-empty mask word
+      const bool has = (w0 | w1) != 0ull;
+      const bool in0 = w0 != 0ull;
+      const unsigned long long w = in0 ? w0 : w1;
+      const unsigned long long rest = w & (w - 1);
+      const int i0 = has ? (in0 ? 0 : 64) + (int)__builtin_ctzll(w) : 0;
+      w0 = in0 ? rest : w0;
+      w1 = in0 ? w1 : rest;
+      const float z0 = L.sz[i0];
+      const Verdict vd = dl_test(z0, z1, t12, C);
+      // ambiguous combinations are queued too, marked; the r_tc stage
+      // decides them in float64 (rare), so the rounds carry no branch
+      const bool pass = has && (vd.pass || vd.amb);
+      const unsigned long long bm = ballot(pass);
+      if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16) | (vd.amb ? kDlAmbiguous : 0u);
+      nq += __popcll(bm);
+      if (nq >= kWave) {
+        __syncthreads();
+        test(kWave);
+        const int rem = nq - kWave;
+        const uint32_t v = lane < rem ? L.sjoin[kWave + lane] : 0u;
+        __syncthreads();
+        if (lane < rem) L.sjoin[lane] = v;
+        __syncthreads();
+        nq = rem;
+      }
+    }
+  };
+  // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
+  int npend = 0;
+  const int n12 = n1 * n2;
+  const float r2 = __builtin_amdgcn_rcpf((float)n2);
+  for (int base = 0; base < n12; base += kWave) {
+    const int p = base + lane;
+    const bool inr = p < n12;
+    const int i1 = inr ? (int)(((float)p + 0.5f) * r2) : 0;
+    const int i2 = inr ? p - i1 * n2 : 0;
+    const bool act = inr && (L.sm01[W * i1] | (W == 2 ? L.sm01[W * i1 + 1] : 0ull)) != 0ull;
+    // pairs float32 cannot decide are queued too, marked, and decided in
+    // float64 by the r_t,c stage for the combinations that reach it
+    const Verdict v = cos_test(L.sx[TT + i1], L.sy[TT + i1], L.sx[2 * TT + i2], L.sy[2 * TT + i2], C.invRR12,
+                               C.c12_lo, C.c12_hi);
+    const bool pass = act && (v.pass || v.amb);
+    const unsigned long long bm = ballot(pass);
+    if (pass) L.spend[npend + rank_below(bm)] = (uint32_t)i1 | ((uint32_t)i2 << 8) | (v.amb ? kPhi12Ambiguous : 0u);
+    npend += __popcll(bm);
+    if (npend >= kWave) {
+      __syncthreads();
+      join(kWave);
+      const int rem = npend - kWave;
+      const uint32_t v = lane < rem ? L.spend[kWave + lane] : 0u;
+      __syncthreads();
+      if (lane < rem) L.spend[lane] = v;
+      __syncthreads();
+      npend = rem;
+    }
+  }
+  if (npend > 0) { __syncthreads(); join(npend); }
+  if (nq > 0) { __syncthreads(); test(nq); }
+  return total;
+}
+
+// A frame with a layer above TT hits (LDS overflow), tile by tile: tiles of
+// at most TT hits per layer, in the order (layer-1 tile, layer-0 tile,
+// layer-2 tile); each (layer-0, layer-1) tile pair builds its Phi01 masks
+// once for all layer-2 tiles.  Returns the number of survivors.  Only k_tiles
+// runs it, so that its loop state stays out of the common one-tile path.
+template <int TT>
+__device__ __attribute__((always_inline)) inline int cut_tiles(int f, int b0, int b1, int b2, int n0, int n1, int n2,
+                                                               const float* __restrict__ X,
+                                                               const float* __restrict__ Y,
+                                                               const float* __restrict__ Z, const Consts& C,
+                                                               CutLds<TT>& L, const TripList& T, Cursor& cur,
+                                                               int& done, int32_t* __restrict__ counters) {
+  constexpr int W = CutLds<TT>::W;
+  const int lane = threadIdx.x;
+  int total = 0;
+  auto stage_layer = [&](int l, int src, int m) {
+    for (int i = lane; i < m; i += kWave) {
+      L.sx[l * TT + i] = X[src + i];
+      L.sy[l * TT + i] = Y[src + i];
+      L.sz[l * TT + i] = Z[src + i];
+    }
+  };
+  for (int a1 = 0; a1 < n1; a1 += TT) {
+    const int m1 = min(TT, n1 - a1);
+    for (int a0 = 0; a0 < n0; a0 += TT) {
+      const int m0 = min(TT, n0 - a0);
+      __syncthreads();
+      stage_layer(0, b0 + a0, m0);
+      stage_layer(1, b1 + a1, m1);
+      for (int i = lane; i < W * m1; i += kWave) L.sm01[i] = 0ull;
+      __syncthreads();
+      phi01_tile<TT>(m0, m1, C, L);
+      for (int a2 = 0; a2 < n2; a2 += TT) {
+        const int m2 = min(TT, n2 - a2);
+        __syncthreads();
+        stage_layer(2, b2 + a2, m2);
+        __syncthreads();
+        total += join_tile<TT>(f, m1, m2, a0, a1, a2, C, L, T, cur, done, counters);
+      }
+    }
+  }
+  return total;
+}
+
 // Selection Cuts of frame f by one wave (Alg. 2): the frame's layer-0..2
-// hits are staged in LDS; a 128-bit mask of layer-0 partners passing Phi01
-// per layer-1 hit; (h1, h2) pairs passing Phi12 are streamed through an LDS
-// queue and each full wave of pairs is joined against its Phi01 partners
-// (Delta lambda tested as they are expanded), the combinations passing it
-// queued and tested on r_tc a full wave at a time.  Survivors are ballot-compacted into the
-// wave's chunks of the triplet list (cur; done = the wave's fitted prefix of
-// its current chunk, recorded when the chunk is closed); returns the number
+// hits are staged in LDS; survivors are ballot-compacted into the wave's
+// chunks of the triplet list (cur; done = the wave's fitted prefix of its
+// current chunk, recorded when the chunk is closed); returns the number
 // committed (0 when the frame overflows max_triplets) and writes the frame's
-// flags and counts.
-__device__ __attribute__((always_inline)) inline int cut_frame(int f, const FrameRegs& R, const float* __restrict__ X, const float* __restrict__ Y,
-                         const float* __restrict__ Z, int n_hits, const Consts& C,
-                         CutLds& L, const TripList& T, Cursor& cur, int& done,
-                         uint32_t* __restrict__ flags, int32_t* __restrict__ counts, float* __restrict__ vtx,
-                         int32_t* __restrict__ ccnt, int32_t* __restrict__ counters) {
+// flags and counts.  A frame with a layer above TT hits is appended to the
+// deferred list (counters[12] entries) for k_tiles instead.
+template <int TT>
+__device__ __attribute__((always_inline)) inline int cut_frame(int f, const FrameRegs& R, const float* __restrict__ X,
+                                                               const float* __restrict__ Y,
+                                                               const float* __restrict__ Z, int n_hits,
+                                                               const Consts& C, CutLds<TT>& L, const TripList& T,
+                                                               Cursor& cur, int& done, uint32_t* __restrict__ flags,
+                                                               int32_t* __restrict__ counts, float* __restrict__ vtx,
+                                                               int32_t* __restrict__ ccnt,
+                                                               int32_t* __restrict__ counters,
+                                                               int32_t* __restrict__ defer) {
+  constexpr int W = CutLds<TT>::W;
   const int lane = threadIdx.x;
   const int b0 = lane_value(R.lo, 0), b1 = lane_value(R.lo, 1), b2 = lane_value(R.lo, 2);
   const int b3 = lane_value(R.lo, 3), b4 = lane_value(R.lo, 4);
@@ -330,159 +552,37 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     if (lane == 0) { flags[f] = MU3E_HITS_OVF | MU3E_KEEP; counts[3 * f] = 0; }
     return 0;
   }
-  // ---- stage the layer-0..2 hits of the frame (coalesced), clear the masks.
-  // Hits 0..63 arrive in registers loaded during the previous frame; the
-  // rest are loaded in a loop of their own, so that the common case waits
-  // on no memory load here (a wait would also cover the next frame's loads,
-  // issued just before this frame).
-  const int n012 = n0 + n1 + n2;
-  auto stage = [&](int i, float x, float y, float z) {
-    const int l = (i >= n0) + (i >= n0 + n1);
-    const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
-    L.sx[l * kMaxLayerHits + k] = x;
-    L.sy[l * kMaxLayerHits + k] = y;
-    L.sz[l * kMaxLayerHits + k] = z;
-  };
-  if (lane < n012) stage(lane, R.x, R.y, R.z);
-  for (int i = kWave + lane; i < n012; i += kWave) stage(i, X[b0 + i], Y[b0 + i], Z[b0 + i]);
-  for (int i = lane; i < 2 * n1; i += kWave) L.sm01[i] = 0ull;
-  __syncthreads();
   int total = 0;   // triplets passing all cuts (exact)
   const int fid = cur.id, fused = cur.used;   // where this frame's entries begin
-  if (n0 > 0 && n2 > 0) {
-    // ---- Phi01 over all (i0, i1) pairs
-    const int n01 = n0 * n1;
-    // hardware reciprocal (about 1 ulp): (p + 0.5) / n0 stays at least
-    // 0.5 / n0 >= 1/256 from an integer, far above its rounding error, so the
-    // truncation below is exact
-    const float r0 = __builtin_amdgcn_rcpf((float)n0);
-    for (int base = 0; base < n01; base += kWave) {
-      const int p = base + lane;
-      const bool act = p < n01;
-      const int i1 = act ? (int)(((float)p + 0.5f) * r0) : 0;   // exact for p < 2^14
-      const int i0 = act ? p - i1 * n0 : 0;
-      if (cos_cut_wave(act, L.sx[i0], L.sy[i0], L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], C.invRR01,
-                       C.c01_lo, C.c01_hi, C.R[0], C.R[1]))
-        atomicOr(&L.sm01[2 * i1 + (i0 >> 6)], 1ull << (i0 & 63));
+  if (n0 > 0 && n2 > 0 && n1 > 0) {
+    if (n0 <= TT && n1 <= TT && n2 <= TT) {
+      // ---- one tile (the common case): stage the layer-0..2 hits
+      // (coalesced), clear the masks.  Hits 0..63 arrive in registers loaded
+      // during the previous frame; the rest are loaded in a loop of their
+      // own, so that the common case waits on no memory load here (a wait
+      // would also cover the next frame's loads, issued just before this
+      // frame).
+      const int n012 = n0 + n1 + n2;
+      auto stage = [&](int i, float x, float y, float z) {
+        const int l = (i >= n0) + (i >= n0 + n1);
+        const int k = i - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
+        L.sx[l * TT + k] = x;
+        L.sy[l * TT + k] = y;
+        L.sz[l * TT + k] = z;
+      };
+      if (lane < n012) stage(lane, R.x, R.y, R.z);
+      for (int i = kWave + lane; i < n012; i += kWave) stage(i, X[b0 + i], Y[b0 + i], Z[b0 + i]);
+      for (int i = lane; i < W * n1; i += kWave) L.sm01[i] = 0ull;
+      __syncthreads();
+      phi01_tile<TT>(n0, n1, C, L);
+      __syncthreads();
+      total = join_tile<TT>(f, n1, n2, 0, 0, 0, C, L, T, cur, done, counters);
+    } else {
+      // ---- LDS overflow: the frame is deferred to k_tiles, which runs it
+      // tile by tile and writes its flags and triplet count
+      if (lane == 0) defer[atomicAdd(&counters[12], 1)] = f;
+      return 0;
     }
-    __syncthreads();
-    // r_tc test of the first m (<= kWave) queued combinations, one per lane
-    // (with the float64 Phi12 and Delta lambda decisions of those marked
-    // ambiguous);
-    // survivors are ballot-compacted into the wave's chunks of the list.
-    auto test = [&](int m) {
-      const bool act = lane < m;
-      const uint32_t c3 = act ? L.sjoin[lane] : 0u;
-      const int j1 = c3 & 0xff, j2 = (c3 >> 8) & 0xff, j0 = (c3 >> 16) & 0xff;
-      const float x0 = L.sx[j0], y0 = L.sy[j0];
-      const float x1 = L.sx[kMaxLayerHits + j1], y1 = L.sy[kMaxLayerHits + j1];
-      const float x2 = L.sx[2 * kMaxLayerHits + j2], y2 = L.sy[2 * kMaxLayerHits + j2];
-      const Verdict vr = rtc_test(x0, y0, x1, y1, x2, y2, C);
-      bool rpass = vr.pass;
-      const bool damb = act && (c3 & kDlAmbiguous), pamb = act && (c3 & kPhi12Ambiguous);
-      if (ballot(damb || pamb || (act && vr.amb)) != 0ull) {   // rare: float64 where float32 cannot decide
-        if ((pamb && !cos_refine(x1, y1, x2, y2, C.c12_lo, C.c12_hi, C.R[1], C.R[2])) ||
-            (damb && !dl_refine(L.sz[j0], L.sz[kMaxLayerHits + j1], L.sz[2 * kMaxLayerHits + j2], C.R[0], C.R[1],
-                                C.R[2], C.dl_lo, C.dl_hi)))
-          rpass = false;
-        else if (act && vr.amb)
-          rpass = rtc_refine(x0, y0, x1, y1, x2, y2, C.rtc_lo, C.rtc_hi);
-      }
-      const bool pass = act && rpass;
-      const unsigned long long bm = ballot(pass);
-      const int c = __popcll(bm);
-      if (c > 0) {
-        if (cur.id != kListFull && (cur.id < 0 || cur.used + c > T.chunk)) {
-          cursor_close(cur, done, T);
-          cursor_open(cur, T, counters);
-          done = 0;
-        }
-        if (cur.id >= 0) {
-          if (pass) {
-            const int slot = cur.id * T.chunk + cur.used + rank_below(bm);
-            T.trips[2 * slot] = f;
-            T.trips[2 * slot + 1] = (int32_t)((uint32_t)j0 | ((uint32_t)j1 << 8) | ((uint32_t)j2 << 16));
-          }
-          cur.used += c;
-        }
-      }
-      total += c;
-    };
-    // Join of the k pending (h1, h2) pairs with their Phi01 partners: each
-    // lane visits its pair's partners one per round and tests Delta lambda
-    // (which needs only z); the passing combinations are ballot-compacted
-    // into an LDS queue, and each full wave of them is tested on r_tc, so
-    // that the costly test runs on full waves of the few survivors.
-    int nq = 0;   // queued combinations, < kWave between rounds
-    auto join = [&](int k) {
-      const bool have = lane < k;
-      const uint32_t e = have ? L.spend[lane] : 0u;
-      const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
-      unsigned long long w0 = have ? L.sm01[2 * i1] : 0ull, w1 = have ? L.sm01[2 * i1 + 1] : 0ull;
-      const float z1 = L.sz[kMaxLayerHits + i1], z2 = L.sz[2 * kMaxLayerHits + i2];
-      const float t12 = (z2 - z1) * C.inv12;
-      while (ballot((w0 | w1) != 0ull) != 0ull) {
-        // next partner, taken without a branch: the lowest set bit of the
-        // first non-empty mask word
-        const bool has = (w0 | w1) != 0ull;
-        const bool in0 = w0 != 0ull;
-        const unsigned long long w = in0 ? w0 : w1;
-        const unsigned long long rest = w & (w - 1);
-        const int i0 = has ? (in0 ? 0 : 64) + (int)__builtin_ctzll(w) : 0;
-        w0 = in0 ? rest : w0;
-        w1 = in0 ? w1 : rest;
-        const float z0 = L.sz[i0];
-        const Verdict vd = dl_test(z0, z1, t12, C);
-        // ambiguous combinations are queued too, marked; the r_tc stage
-        // decides them in float64 (rare), so the rounds carry no branch
-        const bool pass = has && (vd.pass || vd.amb);
-        const unsigned long long bm = ballot(pass);
-        if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16) | (vd.amb ? kDlAmbiguous : 0u);
-        nq += __popcll(bm);
-        if (nq >= kWave) {
-          __syncthreads();
-          test(kWave);
-          const int rem = nq - kWave;
-          const uint32_t v = lane < rem ? L.sjoin[kWave + lane] : 0u;
-          __syncthreads();
-          if (lane < rem) L.sjoin[lane] = v;
-          __syncthreads();
-          nq = rem;
-        }
-      }
-    };
-    // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
-    int npend = 0;
-    const int n12 = n1 * n2;
-    const float r2 = __builtin_amdgcn_rcpf((float)n2);
-    for (int base = 0; base < n12; base += kWave) {
-      const int p = base + lane;
-      const bool inr = p < n12;
-      const int i1 = inr ? (int)(((float)p + 0.5f) * r2) : 0;
-      const int i2 = inr ? p - i1 * n2 : 0;
-      const bool act = inr && (L.sm01[2 * i1] | L.sm01[2 * i1 + 1]) != 0ull;
-      // pairs float32 cannot decide are queued too, marked, and decided in
-      // float64 by the r_t,c stage for the combinations that reach it
-      const Verdict v = cos_test(L.sx[kMaxLayerHits + i1], L.sy[kMaxLayerHits + i1], L.sx[2 * kMaxLayerHits + i2],
-                                 L.sy[2 * kMaxLayerHits + i2], C.invRR12, C.c12_lo, C.c12_hi);
-      const bool pass = act && (v.pass || v.amb);
-      const unsigned long long bm = ballot(pass);
-      if (pass)
-        L.spend[npend + rank_below(bm)] = (uint32_t)i1 | ((uint32_t)i2 << 8) | (v.amb ? kPhi12Ambiguous : 0u);
-      npend += __popcll(bm);
-      if (npend >= kWave) {
-        __syncthreads();
-        join(kWave);
-        const int rem = npend - kWave;
-        const uint32_t v = lane < rem ? L.spend[kWave + lane] : 0u;
-        __syncthreads();
-        if (lane < rem) L.spend[lane] = v;
-        __syncthreads();
-        npend = rem;
-      }
-    }
-    if (npend > 0) { __syncthreads(); join(npend); }
-    if (nq > 0) { __syncthreads(); test(nq); }
   }
   const bool ovf = total > C.max_trip;
   if (lane == 0) {
@@ -536,21 +636,63 @@ __device__ inline void frame_pipeline(int first, Next next, Body body, const int
 // Plain form: one wave per frame, frames dealt cyclically to a static grid
 // (Alg. 1 with the paper's cyclic distribution); survivors go to the wave's
 // chunks of the triplet list.
+template <int TT>
 __global__ void __launch_bounds__(64)
 k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
        const int32_t* __restrict__ lo, int F, int n_hits, Consts C, uint32_t* __restrict__ flags,
        int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
-       int32_t* __restrict__ counters, int32_t* __restrict__ claims) {
-  __shared__ CutLds L;
+       int32_t* __restrict__ counters, int32_t* __restrict__ claims, int32_t* __restrict__ defer) {
+  __shared__ CutLds<TT> L;
   Cursor cur = cursor_start(T, (int)blockIdx.x);
   int done = 0, selected = 0;   // nothing is fitted here
   const int G = gridDim.x;
   frame_pipeline(
       (int)blockIdx.x < F ? (int)blockIdx.x : -1, [&](int g) { return g < F - G ? g + G : -1; },
       [&](int f, const FrameRegs& R) {
-        selected += cut_frame(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+        selected += cut_frame<TT>(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters,
+                                  defer);
       },
       lo, X, Y, Z, n_hits);
+  close_list(cur, 0, selected, T, claims);
+}
+
+// Frames the cuts kernel deferred (a layer above TT hits: LDS overflow), one
+// wave per frame, claimed from a counter: the frame runs tile by tile
+// (cut_tiles) and its flags and triplet count are written, with the same
+// cap and roll-back as in cut_frame.  Waves beyond the number of deferred
+// frames return at once, so a batch without such frames costs one empty
+// launch.
+template <int TT>
+__global__ void __launch_bounds__(64)
+k_tiles(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+        const int32_t* __restrict__ lo, Consts C, uint32_t* __restrict__ flags, int32_t* __restrict__ counts,
+        TripList T, int32_t* __restrict__ counters, int32_t* __restrict__ claims,
+        const int32_t* __restrict__ defer) {
+  const int nd = counters[12];
+  if ((int)blockIdx.x >= nd) return;
+  __shared__ CutLds<TT> L;
+  const int lane = threadIdx.x;
+  Cursor cur{kNoChunk, 0};
+  int done = 0, selected = 0;
+  for (;;) {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(&counters[13], 1);
+    k = lane_value(k, 0);
+    if (k >= nd) break;
+    const int f = defer[k];
+    const int b0 = lo[4 * f], b1 = lo[4 * f + 1], b2 = lo[4 * f + 2], b3 = lo[4 * f + 3];
+    const int fid = cur.id, fused = cur.used;
+    const int total = cut_tiles<TT>(f, b0, b1, b2, b1 - b0, b2 - b1, b3 - b2, X, Y, Z, C, L, T, cur, done,
+                                    counters);
+    const bool ovf = total > C.max_trip;
+    if (lane == 0) {
+      counts[3 * f] = total;
+      flags[f] = ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u;
+    }
+    if (ovf && cur.id >= 0) cur.used = cur.id == fid ? fused : 0;
+    selected += ovf ? 0 : total;
+    __syncthreads();
+  }
   close_list(cur, 0, selected, T, claims);
 }
 
@@ -683,8 +825,8 @@ struct EntryHits {
 };
 
 __device__ inline EntryHits entry_hits(const int32_t* __restrict__ lo, int f, uint32_t pk) {
-  return EntryHits{lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
-                   lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3], lo[4 * f + 4]};
+  return EntryHits{lo[4 * f] + (int)(pk & kIdxMask), lo[4 * f + 1] + (int)((pk >> kIdxBits) & kIdxMask),
+                   lo[4 * f + 2] + (int)(pk >> (2 * kIdxBits)), lo[4 * f + 3], lo[4 * f + 4]};
 }
 
 // A list entry of T: {frame, packed frame-local indices}, one 8-byte load.
@@ -839,13 +981,14 @@ k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* 
 // closed in the middle of a frame are recorded for k_tracks.  Without kFuse
 // the kernel needs far fewer registers (more resident waves for the
 // latency-bound cuts) and k_tracks fits everything.
-template <bool kFuse>
+template <bool kFuse, int TT>
 __global__ void __launch_bounds__(64)
 k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
           const int32_t* __restrict__ lo, int F, int Fs, int n_hits, Consts C, uint32_t* __restrict__ flags,
           int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
-          TrackOut O, int32_t* __restrict__ counters, int32_t* __restrict__ claims, int claim) {
-  __shared__ CutLds L;
+          TrackOut O, int32_t* __restrict__ counters, int32_t* __restrict__ claims, int claim,
+          int32_t* __restrict__ defer) {
+  __shared__ CutLds<TT> L;
   const int lane = threadIdx.x;
   Cursor cur = cursor_start(T, (int)blockIdx.x);
   int done = 0, selected = 0;
@@ -865,7 +1008,8 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
     done += k;
   };
   auto body = [&](int f, const FrameRegs& R) {
-    selected += cut_frame(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters);
+    selected += cut_frame<TT>(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters,
+                              defer);
     if constexpr (kFuse) {
       while (cur.used - done >= kWave) fit(kWave);
     }
@@ -1135,10 +1279,20 @@ __device__ inline int wave_sum(int v) {
 // first the energy test and the combination cap, then the vertex estimate of
 // every energy-passing triple and a wave-wide minimum of the vertex chi2
 // (ties to the lowest triple index).  id(j) gives the j-th track slot.
+// Optional record of the energy-passing triples of a frame (debug view of
+// the standalone vertex entry point): rows {frame, track a, track b, track c}
+// (a, b the e+ tracks, c the e- track, as given by id) appended to rows[cap]
+// with the row count at *n.
+struct TripleRec {
+  int32_t* rows;
+  int32_t* n;
+  int cap;
+};
+
 template <class Id>
 __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict__ vt,
                             const int32_t* __restrict__ vok, const Consts& C, uint32_t* __restrict__ flags,
-                            int32_t* __restrict__ ncombo, float* __restrict__ vtx) {
+                            int32_t* __restrict__ ncombo, float* __restrict__ vtx, TripleRec rec = TripleRec{}) {
   __shared__ int spos[kVtxTracks], sneg[kVtxTracks];
   const int lane = threadIdx.x;
   const double elo = kMassMu - (double)C.de_max, ehi = kMassMu + (double)C.de_max;
@@ -1152,7 +1306,12 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
             const int ta = id(a), tb = id(b), te = id(e);
             if (!vok[ta] || !vok[tb] || !vok[te] || vt[ta].q < 0 || vt[tb].q < 0 || vt[te].q > 0) continue;
             const double s = vt[ta].E + vt[tb].E + vt[te].E;
-            cnt += (s >= elo && s <= ehi);
+            const bool ep = s >= elo && s <= ehi;
+            cnt += ep;
+            if (ep && rec.rows) {
+              const int r = atomicAdd(rec.n, 1);
+              if (r < rec.cap) *reinterpret_cast<int4*>(rec.rows + 4 * r) = make_int4(f, ta, tb, te);
+            }
           }
       *ncombo = (int32_t)min(cnt, (long long)0x7fffffff);
       if (cnt > C.max_combo) { *flags |= MU3E_COMBO_OVF | MU3E_KEEP; return; }
@@ -1204,11 +1363,24 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
   };
   // ---- energy test over all triples, combination cap
   int cnt = 0;
-  for (int k = lane; k < total; k += kWave) {
-    int ta, tb, te;
-    decode(k, ta, tb, te);
-    const double s = vt[ta].E + vt[tb].E + vt[te].E;
-    cnt += (s >= elo && s <= ehi);
+  for (int base = 0; base < total; base += kWave) {
+    const int k = base + lane;
+    int ta = 0, tb = 0, te = 0;
+    bool ep = false;
+    if (k < total) {
+      decode(k, ta, tb, te);
+      const double s = vt[ta].E + vt[tb].E + vt[te].E;
+      ep = s >= elo && s <= ehi;
+    }
+    cnt += ep;
+    if (rec.rows) {   // debug record (wave-uniform pointer)
+      const unsigned long long bm = ballot(ep);
+      int r0 = 0;
+      if (bm != 0ull && lane == 0) r0 = atomicAdd(rec.n, __popcll(bm));
+      r0 = lane_value(r0, 0);
+      const int r = r0 + rank_below(bm);
+      if (ep && r < rec.cap) *reinterpret_cast<int4*>(rec.rows + 4 * r) = make_int4(f, ta, tb, te);
+    }
   }
   cnt = wave_sum(cnt);
   if (lane == 0) *ncombo = cnt;
@@ -1407,8 +1579,8 @@ k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* _
     const int pos = atomicAdd(&vpos[f], 1);
     if (b + pos >= vcap) continue;   // table full: reported by k_vplace
     const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
-    const int32_t h[4] = {lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
-                          lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3] + res[4 * e + 1]};
+    const EntryHits eh = entry_hits(lo, f, pk);
+    const int32_t h[4] = {eh.g0, eh.g1, eh.g2, eh.b3 + res[4 * e + 1]};
     vok[b + pos] = vtrack_make(X, Y, Z, n_hits, h, C, vt[b + pos]) ? 1 : 0;
   }
 }
@@ -1441,8 +1613,8 @@ k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const f
       if (lane < nt) {
         const int e = tslot[f * kTrackSlots + lane];
         const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
-        const int32_t h[4] = {lo[4 * f] + (int)(pk & 0xff), lo[4 * f + 1] + (int)((pk >> 8) & 0xff),
-                              lo[4 * f + 2] + (int)((pk >> 16) & 0xff), lo[4 * f + 3] + res[4 * e + 1]};
+        const EntryHits eh = entry_hits(lo, f, pk);
+        const int32_t h[4] = {eh.g0, eh.g1, eh.g2, eh.b3 + res[4 * e + 1]};
         VTrack v;
         svok[lane] = vtrack_make(X, Y, Z, n_hits, h, C, v) ? 1 : 0;
         svt[lane] = v;
@@ -1467,7 +1639,7 @@ k_vprep_range(const float* __restrict__ X, const float* __restrict__ Y, const fl
 __global__ void __launch_bounds__(64)
 k_vframes_range(int F, int n_tracks, Consts C, const int32_t* __restrict__ off, const VTrack* __restrict__ vt,
                 const int32_t* __restrict__ vok, uint32_t* __restrict__ flags, int32_t* __restrict__ combos,
-                float* __restrict__ vtx) {
+                float* __restrict__ vtx, TripleRec rec) {
   const int lane = threadIdx.x;
   for (int f = blockIdx.x; f < F; f += gridDim.x) {
     if (lane < 4) vtx[4 * f + lane] = __builtin_nanf("");
@@ -1482,7 +1654,7 @@ k_vframes_range(int F, int n_tracks, Consts C, const int32_t* __restrict__ off, 
       __shared__ int32_t snc;
       if (lane == 0) { sfl = 0; snc = 0; }
       __syncthreads();
-      vertex_wave(f, nt, RangeId{b}, vt, vok, C, &sfl, &snc, vtx + 4 * f);
+      vertex_wave(f, nt, RangeId{b}, vt, vok, C, &sfl, &snc, vtx + 4 * f, rec);
       __syncthreads();
       fl = sfl;
       nc = snc;
@@ -1622,7 +1794,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t counters, claims, chunks, trips, res, sfit, sall, sblk, redo, vt, vok, ccnt, vbase, vpos, cand, vblk, tslot,
-      total;
+      defer, total;
 };
 
 // Entries of each slice table: at most ceil(count / 64) slices per chunk.
@@ -1648,6 +1820,7 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.cand = o; o += align256((size_t)F * sizeof(int32_t));
   L.vblk = o; o += align256((size_t)3 * kVBlocks * sizeof(int32_t));
   L.tslot = o; o += align256((size_t)F * kTrackSlots * sizeof(int32_t));
+  L.defer = o; o += align256((size_t)F * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -1688,7 +1861,8 @@ int device_cus() {
 
 // Pointers into a caller workspace.
 struct WsView {
-  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok, *vblk, *sblk, *tslot;
+  int32_t *counters, *claims, *chunks, *trips, *res, *redo, *ccnt, *vbase, *vpos, *cand, *vok, *vblk, *sblk, *tslot,
+      *defer;
   Slices S;
   VTrack* vt;
   int redo_cap;
@@ -1714,6 +1888,7 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.cand = reinterpret_cast<int32_t*>(ws + L.cand);
   W.vblk = reinterpret_cast<int32_t*>(ws + L.vblk);
   W.tslot = reinterpret_cast<int32_t*>(ws + L.tslot);
+  W.defer = reinterpret_cast<int32_t*>(ws + L.defer);
   W.redo_cap = track_capacity / 8 + 1024;
   return W;
 }
@@ -1743,6 +1918,18 @@ TripList trip_list(const WsView& W, int capacity, int waves) {
   T.chunk = (int)c;
   T.pre = waves < capacity / T.chunk ? waves : capacity / T.chunk;
   return T;
+}
+
+// Deferred frames (a layer above the LDS tile) after the cuts kernel of
+// either form; a grid of 4 waves per CU claims them one at a time.
+void launch_tiles(const mu3e_hits_t& h, const Consts& C, int cus, int tile, const WsView& W, const TripList& T,
+                  uint32_t* flags, int32_t* counts, hipStream_t stream) {
+  if (tile == 64)
+    hipLaunchKernelGGL(k_tiles<64>, dim3(cus * 4), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, flags,
+                       counts, T, W.counters, W.claims, W.defer);
+  else
+    hipLaunchKernelGGL(k_tiles<128>, dim3(cus * 4), dim3(kWave), 0, stream, h.x, h.y, h.z, h.layer_offsets, C, flags,
+                       counts, T, W.counters, W.claims, W.defer);
 }
 
 // Track stage after the cuts of either form: slice tables, float32 fits of
@@ -1826,7 +2013,7 @@ mu3e_status select_impl(const mu3e_hits_t* hits, const mu3e_params_t* params, ui
     return MU3E_ERR_INVALID_ARG;
   Consts C;
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
-  if (C.max_lh > kMaxLayerHits) return MU3E_ERR_UNSUPPORTED;
+  if (C.max_lh > kMaxTiledLayerHits) return MU3E_ERR_UNSUPPORTED;
   const int F = hits->n_frames;
   const Layout L = layout(F, triplet_capacity, track_capacity);
   if (!workspace || workspace_bytes < L.total) return MU3E_ERR_CAPACITY;
@@ -1850,8 +2037,10 @@ mu3e_status select_impl(const mu3e_hits_t* hits, const mu3e_params_t* params, ui
     for (int k = 1; ev && k < 5; ++k) (void)hipEventRecord(ev[k], stream);
     return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
   }
-  hipLaunchKernelGGL(k_cuts, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets, F,
-                     hits->n_hits, C, frame_flags, frame_counts, frame_vertex, W.ccnt, T, W.counters, W.claims);
+  hipLaunchKernelGGL(k_cuts<kPlainTile>, dim3(g1), dim3(kWave), 0, stream, hits->x, hits->y, hits->z,
+                     hits->layer_offsets, F, hits->n_hits, C, frame_flags, frame_counts, frame_vertex, W.ccnt, T,
+                     W.counters, W.claims, W.defer);
+  launch_tiles(*hits, C, cus, kPlainTile, W, T, frame_flags, frame_counts, stream);
   if (ev) (void)hipEventRecord(ev[1], stream);
   launch_tracks(*hits, C, cus, W, T, frame_flags, frame_counts, stream, nullptr);
   if (ev) (void)hipEventRecord(ev[2], stream);
@@ -1914,7 +2103,6 @@ mu3e_status mu3e_select_frames_static(const mu3e_hits_t* hits, const mu3e_params
                      track_capacity, dbg, stream, nullptr);
 }
 
-
 mu3e_status mu3e_fit_triplets(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const mu3e_params_t* params,
                               float* out, hipStream_t stream) {
   if (!hits || hits->n_hits < 0 || n < 0 || !params || (n > 0 && (!trip || !out || !hits->x || !hits->y || !hits->z)))
@@ -1934,10 +2122,12 @@ size_t mu3e_vertex_workspace_size(int32_t n_tracks) {
   return align256((size_t)n_tracks * sizeof(VTrack)) + align256((size_t)n_tracks * sizeof(int32_t));
 }
 
-mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, const mu3e_params_t* params,
-                        uint32_t* frame_flags, int32_t* frame_combos, float* frame_vertex, void* workspace,
-                        size_t workspace_bytes, hipStream_t stream) {
-  if (!hits || hits->n_hits < 0 || !tracks || !params || tracks->n_frames < 0 || tracks->n_tracks < 0)
+mu3e_status mu3e_vertex_debug(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, const mu3e_params_t* params,
+                              uint32_t* frame_flags, int32_t* frame_combos, float* frame_vertex, void* workspace,
+                              size_t workspace_bytes, int32_t* triples, int32_t triple_capacity, int32_t* n_triples,
+                              hipStream_t stream) {
+  if (!hits || hits->n_hits < 0 || !tracks || !params || tracks->n_frames < 0 || tracks->n_tracks < 0 ||
+      triple_capacity < 0 || (triples && !n_triples))
     return MU3E_ERR_INVALID_ARG;
   Consts C;
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
@@ -1957,8 +2147,15 @@ mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, co
   }
   const int g = F < cus * 16 ? F : cus * 16;
   hipLaunchKernelGGL(k_vframes_range, dim3(g), dim3(kWave), 0, stream, F, n, C, tracks->frame_offsets, vt, vok,
-                     frame_flags, frame_combos, frame_vertex);
+                     frame_flags, frame_combos, frame_vertex, TripleRec{triples, n_triples, triple_capacity});
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_vertex(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, const mu3e_params_t* params,
+                        uint32_t* frame_flags, int32_t* frame_combos, float* frame_vertex, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream) {
+  return mu3e_vertex_debug(hits, tracks, params, frame_flags, frame_combos, frame_vertex, workspace, workspace_bytes,
+                           nullptr, 0, nullptr, stream);
 }
 
 mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t* hits, const int32_t* trip, int32_t n,
@@ -2021,44 +2218,116 @@ mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, in
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
-struct mu3e_plan {
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  mu3e_debug_t dbg;
-  mu3e_tuning_t tuning;
-  // launch arguments, kept so that the same sequence can run eagerly
-  mu3e_hits_t hits;
-  Consts C;
+// The persistent kernel of a plan: fused fits or not, LDS tiles of 64 or 128
+// hits per layer.
+using BatchedFn = void (*)(const float*, const float*, const float*, const int32_t*, int, int, int, Consts,
+                           uint32_t*, int32_t*, float*, int32_t*, TripList, TrackOut, int32_t*, int32_t*, int,
+                           int32_t*);
+static BatchedFn batched_kernel(bool fuse, int tile) {
+  if (tile == 64) return fuse ? k_batched<true, 64> : k_batched<false, 64>;
+  return fuse ? k_batched<true, 128> : k_batched<false, 128>;
+}
+
+constexpr int kMaxParts = 4;   // sub-batches of a plan
+
+// One sub-batch of a plan: a contiguous range of the batch's frames with its
+// own part of the workspace, and two graphs, the cuts (counters cleared,
+// persistent kernel) and the rest (fits, float64 re-evaluation, vertex
+// stage), so that the rest of one sub-batch can overlap the cuts of the next.
+struct PlanPart {
+  mu3e_hits_t hits;   // layer_offsets advanced to the first frame, n_frames of the part
   WsView W;
+  TripList T;
   uint32_t* flags;
   int32_t* counts;
   float* vertex;
-  TripList T;
-  int F, Fs, P, cus, tcap, kcap;
+  int first, F, Fs, P, kcap;
+  mu3e_debug_t dbg;
+  hipGraph_t graph[2];
+  hipGraphExec_t exec[2];
 };
 
-// The batched sequence: clear counters, persistent cuts (and fits), the fits
-// left to k_tracks, float64 re-evaluation, vertex stage.  ev (nullable, 4
-// events): before and after the persistent kernel, after k_tracks, at the end.
-static void plan_launch(const mu3e_plan& pl, hipStream_t s, hipEvent_t* ev) {
-  const mu3e_hits_t& h = pl.hits;
-  const TrackOut O = track_out(pl.W, pl.counts);
-  hipLaunchKernelGGL(k_init, dim3(kClaimRanges), dim3(256), 0, s, pl.W.counters, pl.T.pre * pl.T.chunk, pl.W.claims);
-  if (pl.F == 0) return;
-  if (ev) (void)hipEventRecord(ev[0], s);
-  if (pl.tuning.fuse_fits)
-    hipLaunchKernelGGL(k_batched<true>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, pl.Fs,
-                       h.n_hits, pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
-                       pl.W.claims, pl.tuning.frames_per_claim);
-  else
-    hipLaunchKernelGGL(k_batched<false>, dim3(pl.P), dim3(kWave), 0, s, h.x, h.y, h.z, h.layer_offsets, pl.F, pl.Fs,
-                       h.n_hits, pl.C, pl.flags, pl.counts, pl.vertex, pl.W.ccnt, pl.T, O, pl.W.counters,
-                       pl.W.claims, pl.tuning.frames_per_claim);
-  if (ev) (void)hipEventRecord(ev[1], s);
+struct mu3e_plan {
+  mu3e_tuning_t tuning;
+  Consts C;
+  int cus, nparts;
+  PlanPart part[kMaxParts];
+  hipStream_t side[kMaxParts];   // streams of parts 1 .. nparts-1
+  hipEvent_t cuts_done[kMaxParts], part_done[kMaxParts];
+};
+
+// Frames, capacities and workspace offset of part j of a plan over F frames
+// (sizes split evenly; each part's workspace laid out as for
+// mu3e_select_workspace_size).
+struct PartSplit {
+  int first, F, tcap, kcap;
+  size_t offset, bytes;
+};
+
+static PartSplit part_split(int F, int tcap, int kcap, int n, int j) {
+  PartSplit q;
+  size_t off = 0;
+  for (int k = 0; k <= j; ++k) {
+    q.first = (int)((int64_t)F * k / n);
+    q.F = (int)((int64_t)F * (k + 1) / n) - q.first;
+    q.tcap = (int)((int64_t)tcap * (k + 1) / n - (int64_t)tcap * k / n);
+    q.kcap = (int)((int64_t)kcap * (k + 1) / n - (int64_t)kcap * k / n);
+    q.offset = off;
+    q.bytes = align256(layout(q.F, q.tcap, q.kcap).total);
+    off += q.bytes;
+  }
+  return q;
+}
+
+static size_t plan_bytes(int F, int tcap, int kcap, int n) {
+  const PartSplit q = part_split(F, tcap, kcap, n, n - 1);
+  return n == 1 ? layout(F, tcap, kcap).total : q.offset + q.bytes;
+}
+
+// The batched sequence of one part: stage 0 clears the counters and runs
+// the persistent cuts (and fits); stage 1 the fits left to k_tracks, the
+// float64 re-evaluation and the vertex stage.  ev (nullable, 4 events):
+// before and after the persistent kernel, after k_tracks, at the end.
+static void part_launch(const mu3e_plan& pl, const PlanPart& q, int stage, hipStream_t s, hipEvent_t* ev) {
+  const mu3e_hits_t& h = q.hits;
+  if (stage == 0) {
+    hipLaunchKernelGGL(k_init, dim3(kClaimRanges), dim3(256), 0, s, q.W.counters, q.T.pre * q.T.chunk, q.W.claims);
+    if (q.F == 0) return;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    const TrackOut O = track_out(q.W, q.counts);
+    hipLaunchKernelGGL(batched_kernel(pl.tuning.fuse_fits != 0, pl.tuning.tile_hits), dim3(q.P), dim3(kWave), 0, s,
+                       h.x, h.y, h.z, h.layer_offsets, q.F, q.Fs, h.n_hits, pl.C, q.flags, q.counts, q.vertex,
+                       q.W.ccnt, q.T, O, q.W.counters, q.W.claims, pl.tuning.frames_per_claim, q.W.defer);
+    launch_tiles(h, pl.C, pl.cus, pl.tuning.tile_hits, q.W, q.T, q.flags, q.counts, s);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    return;
+  }
+  if (q.F == 0) return;
   // fits left by the persistent kernel (all of them without fusion)
-  launch_tracks(h, pl.C, pl.cus, pl.W, pl.T, pl.flags, pl.counts, s, ev ? ev[2] : nullptr);
-  launch_vertex(h, pl.C, pl.F, pl.cus, pl.W, pl.T, pl.flags, pl.counts, pl.vertex, pl.kcap, s, nullptr);
+  launch_tracks(h, pl.C, pl.cus, q.W, q.T, q.flags, q.counts, s, ev ? ev[2] : nullptr);
+  launch_vertex(h, pl.C, q.F, pl.cus, q.W, q.T, q.flags, q.counts, q.vertex, q.kcap, s, nullptr);
   if (ev) (void)hipEventRecord(ev[3], s);
+}
+
+static void plan_free(mu3e_plan* pl) {
+  for (int j = 0; j < kMaxParts; ++j) {
+    for (int g = 0; g < 2; ++g) {
+      if (pl->part[j].exec[g]) (void)hipGraphExecDestroy(pl->part[j].exec[g]);
+      if (pl->part[j].graph[g]) (void)hipGraphDestroy(pl->part[j].graph[g]);
+    }
+    if (pl->side[j]) (void)hipStreamDestroy(pl->side[j]);
+    if (pl->cuts_done[j]) (void)hipEventDestroy(pl->cuts_done[j]);
+    if (pl->part_done[j]) (void)hipEventDestroy(pl->part_done[j]);
+  }
+  delete pl;
+}
+
+size_t mu3e_plan_workspace_size(int32_t n_frames, int32_t triplet_capacity, int32_t track_capacity,
+                                int32_t sub_batches) {
+  if (n_frames < 0 || triplet_capacity < 0 || triplet_capacity > kMaxTripletCapacity || track_capacity < 0 ||
+      sub_batches < 0 || sub_batches > kMaxParts)
+    return 0;
+  return plan_bytes(n_frames, triplet_capacity, track_capacity, sub_batches > 0 ? sub_batches : 1);
 }
 
 mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const mu3e_params_t* params,
@@ -2071,76 +2340,128 @@ mu3e_status mu3e_plan_create(mu3e_plan_t** out, const mu3e_hits_t* hits, const m
   *out = nullptr;
   Consts C;
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
-  if (C.max_lh > kMaxLayerHits) return MU3E_ERR_UNSUPPORTED;
-  const int F = hits->n_frames;
-  const Layout L = layout(F, triplet_capacity, track_capacity);
-  if (!workspace || workspace_bytes < L.total) return MU3E_ERR_CAPACITY;
-  if (F > 0 && (!frame_flags || !frame_counts || !frame_vertex)) return MU3E_ERR_INVALID_ARG;
-  const WsView W = ws_view(workspace, L, track_capacity);
-  const int cus = device_cus();
+  if (C.max_lh > kMaxTiledLayerHits) return MU3E_ERR_UNSUPPORTED;
   mu3e_tuning_t t;
   t.waves_per_cu = tuning && tuning->waves_per_cu > 0 ? tuning->waves_per_cu : 16;
   t.frames_per_claim = tuning && tuning->frames_per_claim > 0 ? tuning->frames_per_claim : 4;
   t.fuse_fits = tuning ? (tuning->fuse_fits != 0) : 0;
   t.steal_percent = tuning ? tuning->steal_percent : 0;
-  if (t.steal_percent < 0 || t.steal_percent > 100) return MU3E_ERR_INVALID_ARG;
+  t.tile_hits = tuning && tuning->tile_hits > 0 ? tuning->tile_hits : kPlainTile;
+  t.sub_batches = tuning && tuning->sub_batches > 0 ? tuning->sub_batches : 1;
+  if (t.steal_percent < 0 || t.steal_percent > 100 || (t.tile_hits != 64 && t.tile_hits != 128) ||
+      t.sub_batches > kMaxParts)
+    return MU3E_ERR_INVALID_ARG;
+  const int F = hits->n_frames;
+  if (t.sub_batches > F) t.sub_batches = F > 0 ? F : 1;
+  const int n = t.sub_batches;
+  if (!workspace || workspace_bytes < plan_bytes(F, triplet_capacity, track_capacity, n)) return MU3E_ERR_CAPACITY;
+  if (F > 0 && (!frame_flags || !frame_counts || !frame_vertex)) return MU3E_ERR_INVALID_ARG;
+  const int cus = device_cus();
   // persistent: never more waves than can be resident at once
   int resident = 0;
-  const hipError_t oe = t.fuse_fits
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batched<true>, kWave, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batched<false>, kWave, 0);
+  const hipError_t oe =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batched_kernel(t.fuse_fits != 0, t.tile_hits), kWave, 0);
   if (oe != hipSuccess) return MU3E_ERR_HIP;
   if (resident > 0 && t.waves_per_cu > resident) t.waves_per_cu = resident;
-  int P = cus * t.waves_per_cu;
-  if (P > F) P = F > 0 ? F : 1;
-  mu3e_plan* pl = new (std::nothrow) mu3e_plan;
+  mu3e_plan* pl = new (std::nothrow) mu3e_plan();
   if (!pl) return MU3E_ERR_CAPACITY;
   pl->tuning = t;
-  pl->dbg.counters = W.counters; pl->dbg.triplets = W.trips; pl->dbg.tracks = W.res;
-  pl->dbg.triplet_capacity = triplet_capacity; pl->dbg.track_capacity = track_capacity;
-  pl->hits = *hits; pl->C = C; pl->W = W;
-  pl->flags = frame_flags; pl->counts = frame_counts; pl->vertex = frame_vertex;
-  pl->T = trip_list(W, triplet_capacity, P);
-  pl->dbg.chunks = W.chunks; pl->dbg.max_chunks = triplet_capacity / kMinChunk + 1; pl->dbg.chunk_size = pl->T.chunk;
-  pl->F = F; pl->P = P; pl->cus = cus; pl->tcap = triplet_capacity; pl->kcap = track_capacity;
-  pl->Fs = F - (int)((int64_t)F * t.steal_percent / 100);
-  hipStream_t cs;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return MU3E_ERR_HIP; }
-  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-  if (ok) {
-    plan_launch(*pl, cs, nullptr);
-    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
+  pl->C = C;
+  pl->cus = cus;
+  pl->nparts = n;
+  bool ok = true;
+  for (int j = 0; j < n && ok; ++j) {
+    const PartSplit sp = part_split(F, triplet_capacity, track_capacity, n, j);
+    PlanPart& q = pl->part[j];
+    q.hits = *hits;
+    q.hits.n_frames = sp.F;
+    if (F > 0) q.hits.layer_offsets = hits->layer_offsets + 4 * (size_t)sp.first;
+    const Layout L = layout(sp.F, sp.tcap, sp.kcap);
+    q.W = ws_view(static_cast<char*>(workspace) + sp.offset, L, sp.kcap);
+    q.flags = frame_flags ? frame_flags + sp.first : nullptr;
+    q.counts = frame_counts ? frame_counts + 3 * (size_t)sp.first : nullptr;
+    q.vertex = frame_vertex ? frame_vertex + 4 * (size_t)sp.first : nullptr;
+    q.first = sp.first;
+    q.F = sp.F;
+    q.kcap = sp.kcap;
+    q.P = cus * t.waves_per_cu;
+    if (q.P > q.F) q.P = q.F > 0 ? q.F : 1;
+    q.T = trip_list(q.W, sp.tcap, q.P);
+    q.Fs = q.F - (int)((int64_t)q.F * t.steal_percent / 100);
+    q.dbg.counters = q.W.counters; q.dbg.triplets = q.W.trips; q.dbg.tracks = q.W.res;
+    q.dbg.triplet_capacity = sp.tcap; q.dbg.track_capacity = sp.kcap;
+    q.dbg.chunks = q.W.chunks; q.dbg.max_chunks = sp.tcap / kMinChunk + 1; q.dbg.chunk_size = q.T.chunk;
+    if (j > 0) ok = hipStreamCreateWithFlags(&pl->side[j], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&pl->cuts_done[j], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&pl->part_done[j], hipEventDisableTiming) == hipSuccess;
+    for (int g = 0; g < 2 && ok; ++g) {
+      if (g == 1 && q.F == 0) break;   // nothing after the counters are cleared
+      hipStream_t cs;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { ok = false; break; }
+      ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        part_launch(*pl, q, g, cs, nullptr);
+        ok = hipStreamEndCapture(cs, &q.graph[g]) == hipSuccess;
+      }
+      ok = ok && hipGraphInstantiate(&q.exec[g], q.graph[g], nullptr, nullptr, 0) == hipSuccess;
+      (void)hipStreamDestroy(cs);
+    }
   }
-  ok = ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
-  (void)hipStreamDestroy(cs);
-  if (!ok) { delete pl; return MU3E_ERR_HIP; }
+  if (!ok) { plan_free(pl); return MU3E_ERR_HIP; }
   *out = pl;
   return MU3E_OK;
 }
 
+// Part 0 runs on the caller's stream, part j > 0 on the plan's stream j;
+// the cuts of part j start when those of part j - 1 are done (they need the
+// whole GPU), the rest of each part follows its cuts on its stream and
+// overlaps the next part's cuts; the caller's stream waits for every part.
 mu3e_status mu3e_plan_run(mu3e_plan_t* plan, hipStream_t stream) {
   if (!plan) return MU3E_ERR_INVALID_ARG;
-  return hipGraphLaunch(plan->exec, stream) == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+  bool ok = true;
+  for (int j = 0; j < plan->nparts && ok; ++j) {
+    PlanPart& q = plan->part[j];
+    hipStream_t s = j == 0 ? stream : plan->side[j];
+    if (j > 0) ok = hipStreamWaitEvent(s, plan->cuts_done[j - 1], 0) == hipSuccess;
+    ok = ok && hipGraphLaunch(q.exec[0], s) == hipSuccess;
+    if (plan->nparts > 1) ok = ok && hipEventRecord(plan->cuts_done[j], s) == hipSuccess;
+    if (q.exec[1]) ok = ok && hipGraphLaunch(q.exec[1], s) == hipSuccess;
+    if (j > 0) ok = ok && hipEventRecord(plan->part_done[j], s) == hipSuccess;
+  }
+  for (int j = 1; j < plan->nparts && ok; ++j) ok = hipStreamWaitEvent(stream, plan->part_done[j], 0) == hipSuccess;
+  return ok ? MU3E_OK : MU3E_ERR_HIP;
 }
 
 mu3e_status mu3e_plan_run_timed(mu3e_plan_t* plan, hipStream_t stream, hipEvent_t* events) {
-  if (!plan || !events || !events[0] || !events[1] || !events[2] || !events[3]) return MU3E_ERR_INVALID_ARG;
-  plan_launch(*plan, stream, events);
+  if (!plan || !events) return MU3E_ERR_INVALID_ARG;
+  for (int k = 0; k < 4 * plan->nparts; ++k)
+    if (!events[k]) return MU3E_ERR_INVALID_ARG;
+  for (int j = 0; j < plan->nparts; ++j) {
+    part_launch(*plan, plan->part[j], 0, stream, events + 4 * j);
+    part_launch(*plan, plan->part[j], 1, stream, events + 4 * j);
+  }
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
 mu3e_status mu3e_plan_info(const mu3e_plan_t* plan, mu3e_debug_t* dbg, mu3e_tuning_t* tuning) {
   if (!plan) return MU3E_ERR_INVALID_ARG;
-  if (dbg) *dbg = plan->dbg;
+  if (dbg) *dbg = plan->part[0].dbg;
   if (tuning) *tuning = plan->tuning;
+  return MU3E_OK;
+}
+
+mu3e_status mu3e_plan_part_info(const mu3e_plan_t* plan, int32_t part, mu3e_debug_t* dbg, int32_t* first_frame,
+                                int32_t* n_frames) {
+  if (!plan || part < 0 || part >= plan->nparts) return MU3E_ERR_INVALID_ARG;
+  if (dbg) *dbg = plan->part[part].dbg;
+  if (first_frame) *first_frame = plan->part[part].first;
+  if (n_frames) *n_frames = plan->part[part].F;
   return MU3E_OK;
 }
 
 void mu3e_plan_destroy(mu3e_plan_t* plan) {
   if (!plan) return;
-  (void)hipGraphExecDestroy(plan->exec);
-  (void)hipGraphDestroy(plan->graph);
-  delete plan;
+  plan_free(plan);
 }
 
 }  // extern "C"

@@ -23,7 +23,7 @@ constexpr double kMassE = 0.51099895;     // MeV
 constexpr double kMassMu = 105.6583755;   // MeV
 constexpr double kPiD = 3.14159265358979323846;
 constexpr float kU32 = 5.9604645e-8f;     // unit roundoff of float32, 2^-24
-constexpr int kMaxLayerHits = 128;
+constexpr int kMaxTiledLayerHits = 1023;   // hits per layer the cuts handle (tiled through LDS)
 
 // Per-launch constants (by value in kernel arguments).
 struct Consts {

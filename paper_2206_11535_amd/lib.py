@@ -63,7 +63,8 @@ class Debug(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("frames_per_claim", ctypes.c_int32),
-                ("fuse_fits", ctypes.c_int32), ("steal_percent", ctypes.c_int32)]
+                ("fuse_fits", ctypes.c_int32), ("steal_percent", ctypes.c_int32), ("tile_hits", ctypes.c_int32),
+                ("sub_batches", ctypes.c_int32)]
 
 
 def make_params(p: dict) -> Params:
@@ -117,6 +118,9 @@ def load(path: str = LIB_PATH):
     L.mu3e_vertex_workspace_size.argtypes = [I]
     L.mu3e_vertex.restype = ctypes.c_int
     L.mu3e_vertex.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Tracks), ctypes.POINTER(Params), P, P, P, P, Z, P]
+    L.mu3e_vertex_debug.restype = ctypes.c_int
+    L.mu3e_vertex_debug.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Tracks), ctypes.POINTER(Params), P, P, P,
+                                    P, Z, P, I, P, P]
     L.mu3e_plan_create.restype = ctypes.c_int
     L.mu3e_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Hits), ctypes.POINTER(Params),
                                    P, P, P, P, Z, I, I, ctypes.POINTER(Tuning)]
@@ -126,6 +130,10 @@ def load(path: str = LIB_PATH):
     L.mu3e_plan_run_timed.argtypes = [P, P, P]
     L.mu3e_plan_info.restype = ctypes.c_int
     L.mu3e_plan_info.argtypes = [P, ctypes.POINTER(Debug), ctypes.POINTER(Tuning)]
+    L.mu3e_plan_workspace_size.restype = Z
+    L.mu3e_plan_workspace_size.argtypes = [I, I, I, I]
+    L.mu3e_plan_part_info.restype = ctypes.c_int
+    L.mu3e_plan_part_info.argtypes = [P, I, ctypes.POINTER(Debug), ctypes.POINTER(I), ctypes.POINTER(I)]
     L.mu3e_plan_destroy.restype = None
     L.mu3e_plan_destroy.argtypes = [P]
     L.mu3e_align_chi2.restype = ctypes.c_int
@@ -206,14 +214,17 @@ class Selector:
         self.params = make_params(params)
         self.tcap = int(triplet_capacity if triplet_capacity is not None else 128 * n_frames + 65536)
         self.kcap = int(track_capacity if track_capacity is not None else 16 * n_frames + 4096)
-        nb = L.mu3e_select_workspace_size(n_frames, self.tcap, self.kcap)
+        nb = self._workspace_bytes()
         if nb == 0 and n_frames > 0:
-            raise Mu3eError(-1, "mu3e_select_workspace_size")
+            raise Mu3eError(-1, "workspace size")
         self.ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
         self.flags = torch.empty(max(n_frames, 1), dtype=torch.int32, device=device)
         self.counts = torch.empty((max(n_frames, 1), 3), dtype=torch.int32, device=device)
         self.vertex = torch.empty((max(n_frames, 1), 4), dtype=torch.float32, device=device)
         self.dbg = Debug()
+
+    def _workspace_bytes(self) -> int:
+        return load().mu3e_select_workspace_size(self.n_frames, self.tcap, self.kcap)
 
     def run(self, hits: DeviceHits, stream=None, events=None):
         """events: optional ctypes array of 5 hipEvent_t recorded between the
@@ -234,13 +245,26 @@ class Selector:
                                             _stream(stream), ctypes.cast(events, ctypes.c_void_p))
         _check(st, "mu3e_select_frames")
 
-    def counters(self):
-        """Device counters (synchronises): [0] triplets selected, [2] status
-        bits, [7] triplet entries handed out in chunks, ..."""
+    def _parts(self):
+        """(debug view, first frame) of each independent part of the
+        workspace: one for the plain form."""
+        return [(self.dbg, 0)]
+
+    def _counters_of(self, d):
         import torch
         n = 11
-        base = self.dbg.counters - self.ws.data_ptr()
+        base = d.counters - self.ws.data_ptr()
         return self.ws[base:base + 4 * n].view(torch.int32).cpu().numpy()
+
+    def counters(self):
+        """Device counters (synchronises): [0] triplets selected, [2] status
+        bits, [7] triplet entries handed out in chunks, ...; over the parts
+        of a batched plan: [0] summed, [2] or-ed, the rest those of part 0."""
+        cs = [self._counters_of(d) for d, _ in self._parts()]
+        c = cs[0].copy()
+        c[0] = sum(int(x[0]) for x in cs)
+        c[2] = np.bitwise_or.reduce([int(x[2]) for x in cs])
+        return c
 
     def lists(self, hits_offsets: np.ndarray):
         """Host copies of the selected triplets and the accepted tracks
@@ -248,32 +272,36 @@ class Selector:
         out.  Returns (triplets [n, 4]: frame, h0, h1, h2; tracks [m, 5]:
         frame, h0..h3; kf [m, 2]: kappa_bar, chi2; counters)."""
         import torch
-        c = self.counters()
         ws = self.ws
-        d = self.dbg
-        nch = min(int(c[7]), d.triplet_capacity) // d.chunk_size if d.chunk_size > 0 else 0
-        cb = d.chunks - ws.data_ptr()
-        ch = ws[cb:cb + 16 * nch].view(torch.int32).cpu().numpy().reshape(-1, 4)
-        tb = d.triplets - ws.data_ptr()
-        allt = ws[tb:tb + 8 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 2)
-        rb = d.tracks - ws.data_ptr()
-        allr = ws[rb:rb + 16 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 4)
-        idx = np.concatenate([np.arange(a, a + n) for a, n in ch[:, :2]]) if nch else np.zeros(0, np.int64)
-        trips = allt[idx]
-        res = allr[idx]
+        trips_l, res_l = [], []
+        for d, first in self._parts():
+            c = self._counters_of(d)
+            nch = min(int(c[7]), d.triplet_capacity) // d.chunk_size if d.chunk_size > 0 else 0
+            cb = d.chunks - ws.data_ptr()
+            ch = ws[cb:cb + 16 * nch].view(torch.int32).cpu().numpy().reshape(-1, 4)
+            tb = d.triplets - ws.data_ptr()
+            allt = ws[tb:tb + 8 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 2)
+            rb = d.tracks - ws.data_ptr()
+            allr = ws[rb:rb + 16 * d.triplet_capacity].view(torch.int32).cpu().numpy().reshape(-1, 4)
+            idx = np.concatenate([np.arange(a, a + n) for a, n in ch[:, :2]]) if nch else np.zeros(0, np.int64)
+            t = allt[idx].copy()
+            t[:, 0] += first
+            trips_l.append(t)
+            res_l.append(allr[idx])
+        trips, res = np.concatenate(trips_l), np.concatenate(res_l)
         flags = self.flags[:self.n_frames].cpu().numpy().view(np.uint32)
         keep = (flags[trips[:, 0]] & TRIPLET_OVF) == 0 if len(trips) else np.zeros(0, bool)
         trips, res = trips[keep], res[keep]
         lo = np.asarray(hits_offsets)
         f = trips[:, 0].astype(np.int64)
         pk = trips[:, 1].astype(np.int64)
-        g = np.stack([lo[4 * f] + (pk & 0xff), lo[4 * f + 1] + ((pk >> 8) & 0xff),
-                      lo[4 * f + 2] + ((pk >> 16) & 0xff)], 1)
+        g = np.stack([lo[4 * f] + (pk & 0x3ff), lo[4 * f + 1] + ((pk >> 10) & 0x3ff),
+                      lo[4 * f + 2] + (pk >> 20)], 1)
         triplets = np.concatenate([f[:, None], g], 1)
         acc = res[:, 0] == 1
         tracks = np.concatenate([triplets[acc], (lo[4 * f[acc] + 3] + res[acc, 1])[:, None]], 1)
         kf = res[acc, 2:4].copy().view(np.float32)
-        return triplets, tracks, kf, c
+        return triplets, tracks, kf, self.counters()
 
     def result(self):
         F = self.n_frames
@@ -282,17 +310,21 @@ class Selector:
 
 
 class BatchedSelector(Selector):
-    """The batched persistent form: one hipGraph launch per batch
-    (mu3e_plan_*).  Same outputs as Selector; the plan binds `hits`."""
+    """The batched persistent form (mu3e_plan_*): per sub-batch two hipGraph
+    launches (cuts; fits and vertex stage).  Same outputs as Selector; the
+    plan binds `hits`."""
 
     def __init__(self, hits: DeviceHits, params: dict, triplet_capacity: int | None = None,
                  track_capacity: int | None = None, device="cuda", waves_per_cu: int = 0,
-                 frames_per_claim: int = 0, fuse_fits: int = 0, steal_percent: int = 0):
+                 frames_per_claim: int = 0, fuse_fits: int = 0, steal_percent: int = 0, tile_hits: int = 0,
+                 sub_batches: int = 0):
+        self.sub_batches = int(sub_batches)
         super().__init__(hits.n_frames, params, triplet_capacity, track_capacity, device)
         L = load()
         self.hits = hits
         self._hs = hits.struct()
-        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim), int(fuse_fits), int(steal_percent))
+        self.tuning = Tuning(int(waves_per_cu), int(frames_per_claim), int(fuse_fits), int(steal_percent),
+                             int(tile_hits), self.sub_batches)
         plan = ctypes.c_void_p()
         _check(L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(self._hs), ctypes.byref(self.params),
                                   _ptr(self.flags), _ptr(self.counts), _ptr(self.vertex), _ptr(self.ws),
@@ -301,17 +333,38 @@ class BatchedSelector(Selector):
         self.plan = plan
         eff = Tuning()
         _check(L.mu3e_plan_info(self.plan, ctypes.byref(self.dbg), ctypes.byref(eff)), "mu3e_plan_info")
-        self.effective = (eff.waves_per_cu, eff.frames_per_claim, eff.fuse_fits, eff.steal_percent)
+        self.effective = (eff.waves_per_cu, eff.frames_per_claim, eff.fuse_fits, eff.steal_percent, eff.tile_hits,
+                          eff.sub_batches)
+        self.parts = []
+        for j in range(eff.sub_batches):
+            d, first, n = Debug(), ctypes.c_int32(), ctypes.c_int32()
+            _check(L.mu3e_plan_part_info(self.plan, j, ctypes.byref(d), ctypes.byref(first), ctypes.byref(n)),
+                   "mu3e_plan_part_info")
+            self.parts.append((d, first.value, n.value))
+
+    def _workspace_bytes(self) -> int:
+        return load().mu3e_plan_workspace_size(self.n_frames, self.tcap, self.kcap, self.sub_batches)
+
+    def _parts(self):
+        return [(d, first) for d, first, _ in self.parts]
+
+    def tuning_dict(self) -> dict:
+        """The shape in effect (after the occupancy and frame-count caps)."""
+        keys = ("waves_per_cu", "frames_per_claim", "fuse_fits", "steal_percent", "tile_hits", "sub_batches")
+        return dict(zip(keys, (int(v) for v in self.effective)))
 
     def run(self, hits: DeviceHits = None, stream=None, events=None):
-        """events: optional ctypes array of 4 hipEvent_t; then the plan's
-        kernels are launched directly (no graph) with the events around the
-        persistent kernel and the fit kernel (mu3e_plan_run_timed)."""
+        """events: optional ctypes array of 4 hipEvent_t per sub-batch; then
+        the plan's kernels are launched directly (no graph, the sub-batches
+        one after another) with the events around each sub-batch's
+        persistent kernel and fit kernel (mu3e_plan_run_timed)."""
         if hits is not None and hits is not self.hits:
             raise ValueError("a plan is bound to the hits it was created with")
         if events is None:
             _check(load().mu3e_plan_run(self.plan, _stream(stream)), "mu3e_plan_run")
         else:
+            if len(events) < 4 * len(self.parts):
+                raise ValueError(f"{len(events)} events for {len(self.parts)} sub-batches (4 each)")
             _check(load().mu3e_plan_run_timed(self.plan, _stream(stream), ctypes.cast(events, ctypes.c_void_p)),
                    "mu3e_plan_run_timed")
 
@@ -386,9 +439,11 @@ def fit_triplets_backward(hits: DeviceHits, trip, params: dict, grad_chi2, grad_
     return grad_xyz[:hits.n_hits]
 
 
-def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=None):
+def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=None, triple_capacity: int = 0):
     """track_hits int32 [n, 4], frame_offsets int32 [F+1] (cuda tensors) ->
-    (flags [F], combos [F], vertex [F, 4])."""
+    (flags [F], combos [F], vertex [F, 4]); with triple_capacity > 0 also
+    the energy-passing triples (mu3e_vertex_debug): int32 [m, 4] rows
+    {frame, e+ track, e+ track, e- track} and the true count m' >= m."""
     import torch
     L = load()
     track_hits = _dev(track_hits, torch.int32, (4,), "track_hits")
@@ -404,9 +459,17 @@ def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=Non
     hs = hits.struct()
     tr = Tracks(track_hits.data_ptr() if n else None, frame_offsets.data_ptr(), F, n)
     pp = make_params(params)
-    _check(L.mu3e_vertex(ctypes.byref(hs), ctypes.byref(tr), ctypes.byref(pp), _ptr(flags), _ptr(combos),
-                         _ptr(vtx), _ptr(ws), ws.numel(), _stream(stream)), "mu3e_vertex")
-    return flags[:F], combos[:F], vtx[:F]
+    if triple_capacity <= 0:
+        _check(L.mu3e_vertex(ctypes.byref(hs), ctypes.byref(tr), ctypes.byref(pp), _ptr(flags), _ptr(combos),
+                             _ptr(vtx), _ptr(ws), ws.numel(), _stream(stream)), "mu3e_vertex")
+        return flags[:F], combos[:F], vtx[:F]
+    rows = torch.empty((int(triple_capacity), 4), dtype=torch.int32, device=dev)
+    nrow = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(L.mu3e_vertex_debug(ctypes.byref(hs), ctypes.byref(tr), ctypes.byref(pp), _ptr(flags), _ptr(combos),
+                               _ptr(vtx), _ptr(ws), ws.numel(), _ptr(rows), int(triple_capacity), _ptr(nrow),
+                               _stream(stream)), "mu3e_vertex_debug")
+    m = int(nrow.item())
+    return flags[:F], combos[:F], vtx[:F], rows[:min(m, int(triple_capacity))], m
 
 
 def align_chi2(hits: DeviceHits, trip, theta, params: dict, stream=None):

@@ -12,7 +12,10 @@ calibrated on truth of the synthetic generator and then frozen here:
   windows are one-sided (true triplets reach cos = 1);
 * energy window, vertex chi2, target distance and momentum sum: the 99th
   percentiles on reconstructed signal decays;
-* max_tracks and max_combos: 256 each (placeholders of this reading).
+* max_tracks and max_combos: 256 each (placeholders of this reading);
+* max_layer_hits: 1023, the most hits per layer the kernels take (larger
+  layers are tiled through LDS up to it); the paper keeps a whole frame in
+  shared memory and has no such limit.
 
 `tests/golden/calibrate_params.py` recomputes the calibrated numbers and a
 test checks that they equal the values below.
@@ -37,7 +40,9 @@ DEFAULT = dict(
     max_triplets=768,
     max_tracks=256,
     max_combos=256,
-    max_layer_hits=128,
+    # capacity of this implementation (frame-local hit indices are packed in
+    # 10 bits), not a rule of the method: a frame above it is kept unprocessed
+    max_layer_hits=1023,
     # calibrated vertex thresholds
     de_max=5.64,
     r_target=19.0,

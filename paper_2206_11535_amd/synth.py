@@ -80,6 +80,8 @@ CONFIGS = {
     4: SynthConfig("pile-up lambda=30", 200_000, 30.0, 20, 0.01, 4),
     5: SynthConfig("nominal lambda=6.4 misaligned", 100_000, 6.4, 5, 0.01, 5,
                    misalign=True),
+    # phase II of the experiment: 1e9 mu/s, ten times the nominal rate
+    6: SynthConfig("phase-II lambda=64", 100_000, 64.0, 5, 0.01, 6),
 }
 
 

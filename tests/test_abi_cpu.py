@@ -65,7 +65,7 @@ def test_host_validation(L):
     # workspace too small
     assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 16, 10, 10, None, None) == -3
     # unsupported layer capacity
-    q = lib.make_params(default_params(max_layer_hits=129))
+    q = lib.make_params(default_params(max_layer_hits=1024))
     assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(q), 1, 1, 1, 1, 1 << 30, 10, 10, None, None) == -4
     # inverted window, negative cap, bad radii
     for bad in (dict(dlambda=(0.5, -0.5)), dict(max_tracks=-1), dict(r_layer=(25.0, 24.0, 73.0, 85.0))):

@@ -10,19 +10,25 @@ from paper_2206_11535_amd import autotune
 
 
 def test_candidates():
-    c = autotune.candidates()
+    c = autotune.cyclic_candidates()
     assert len(c) == len(set(c))
-    # the purely cyclic schedule at every wave count, fused and not
-    for u in autotune.FUSE_FITS:
-        for w in autotune.WAVES_PER_CU:
-            assert (w, 0, u, 0) in c
-    for w, claim, u, st in c:
-        assert u in autotune.FUSE_FITS
-        if st:
-            assert st in autotune.STEAL_PERCENT and claim in autotune.FRAMES_PER_CLAIM
-            assert w in autotune.STEAL_WAVES_PER_CU
-        else:
-            assert claim == 0 and w in autotune.WAVES_PER_CU
+    # the purely cyclic schedule at every wave count, tile size and fusion
+    for t in autotune.TILE_HITS:
+        for u in autotune.FUSE_FITS:
+            for w in autotune.WAVES_PER_CU:
+                assert (w, 0, u, 0, t, 1) in c
+    assert set(autotune.TILE_HITS) == {64, 128}
+    best = (20, 0, 1, 0, 64, 1)
+    s = autotune.steal_candidates(best)
+    assert len(s) == len(set(s))
+    for w, claim, u, st, t, n in s:
+        assert (u, t, n) == (1, 64, 1)
+        assert st in autotune.STEAL_PERCENT and claim in autotune.FRAMES_PER_CLAIM
+        assert w in autotune.STEAL_WAVES_PER_CU or w == 20
+    sp = autotune.split_candidates((8, 4, 0, 25, 128, 1))
+    assert sp == [(8, 4, 0, 25, 128, n) for n in autotune.SUB_BATCHES if n > 1]
+    assert autotune.as_kwargs((8, 4, 0, 25, 128, 2)) == dict(waves_per_cu=8, frames_per_claim=4, fuse_fits=0,
+                                                            steal_percent=25, tile_hits=128, sub_batches=2)
 
 
 def test_workload_key_rounds_hits_per_frame():
@@ -61,18 +67,17 @@ def test_committed_cache_is_well_formed():
     with open(autotune.CACHE) as f:
         cache = json.load(f)
     assert cache
-    shapes = set(autotune.candidates())
     for key, e in cache.items():
         arch, rocm, src, frames, hpf = key.split("|")
         assert arch.startswith("gfx") and rocm.startswith("rocm") and src.startswith("src")
         assert frames.startswith("F") and hpf.startswith("hpf")
-        assert set(e) == {"waves_per_cu", "frames_per_claim", "fuse_fits", "steal_percent", "ms"}
+        assert set(e) == set(autotune.FIELDS) | {"ms"}
         assert e["ms"] > 0
         # the shape in effect may be capped by occupancy below the one asked
-        # for, so only the schedule parameters are checked against the list;
-        # a purely cyclic schedule claims nothing, whatever claim size it reports
-        if e["steal_percent"] == 0:
-            assert any((u, st) == (e["fuse_fits"], 0) for _, _, u, st in shapes)
-        else:
-            assert any((c, u, st) == (e["frames_per_claim"], e["fuse_fits"], e["steal_percent"])
-                       for _, c, u, st in shapes)
+        # for, so only the schedule parameters are checked against the lists
+        assert e["tile_hits"] in autotune.TILE_HITS and e["fuse_fits"] in autotune.FUSE_FITS
+        assert e["sub_batches"] in autotune.SUB_BATCHES
+        assert 1 <= e["waves_per_cu"] <= max(autotune.WAVES_PER_CU)
+        if e["steal_percent"]:
+            assert e["steal_percent"] in autotune.STEAL_PERCENT
+            assert e["frames_per_claim"] in autotune.FRAMES_PER_CLAIM

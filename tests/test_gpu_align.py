@@ -41,6 +41,15 @@ def test_forward_matches_oracle(setup):
     L, _ = oracle.align_loss_grad(fs, trip, th32.astype(np.float64), p, grad=False)
     assert np.all(np.isfinite(chi2))
     assert abs(chi2.astype(np.float64).sum() - L) <= 1e-4 * L
+    # element by element: the oracle's chi2 of each triplet on its own (the
+    # one-triplet loss), within 1e-4 relative with an absolute floor of 1
+    rng = np.random.default_rng(3)
+    pick = rng.choice(len(trip), 3000, replace=False)
+    ref = np.array([oracle.align_loss_grad(fs, trip[i:i + 1], th32.astype(np.float64), p, grad=False)[0]
+                    for i in pick])
+    dev = np.abs(chi2[pick].astype(np.float64) - ref) / np.maximum(np.abs(ref), 1.0)
+    print("alignment forward, element-wise relative deviation (floor 1): max", dev.max(), flush=True)
+    assert dev.max() <= 1e-4
 
 
 @pytest.mark.parametrize("at", ["zero", "random"])
