@@ -28,7 +28,9 @@
  * Errors.  Argument errors are reported synchronously as a negative status
  * and nothing is launched.  Conditions only known on the device (a candidate
  * list in the workspace filled up) are reported in the workspace's status
- * word, readable after the stream has been synchronised (mu3e_debug_t).
+ * word, readable after the stream has been synchronised (mu3e_debug_t), and
+ * every frame they touched carries MU3E_LIST_FULL | MU3E_KEEP: a frame is
+ * either fully processed or kept.
  * Exceeding a *method* cap (max_triplets, max_tracks, max_combos) is not an
  * error: the frame's overflow flag is set and the frame is kept, as the
  * paper's implementation marks such frames for storage.  max_layer_hits is a
@@ -62,8 +64,14 @@ enum {
   MU3E_TRACK_OVF = 4u,     /* more than max_tracks tracks passed chi2 < max    */
   MU3E_COMBO_OVF = 8u,     /* more than max_combos e+e+e- triples passed dE    */
   MU3E_VERTEX = 16u,       /* a signal-like vertex was found                   */
-  MU3E_HITS_OVF = 32u      /* a layer holds more than max_layer_hits hits
+  MU3E_HITS_OVF = 32u,     /* a layer holds more than max_layer_hits hits
                               (a capacity flag, see above)                     */
+  MU3E_LIST_FULL = 64u     /* a workspace list of this call was full before the
+                              frame was done (its selected triplets, the
+                              float64 re-evaluation queue, or the vertex
+                              stage's track table): the frame is kept without
+                              the later stages, never passed on incomplete;
+                              its triplet count stays exact                   */
 };
 
 /* Largest per-layer hit count the kernels process.  Layers are staged in LDS

@@ -348,11 +348,12 @@ __device__ __attribute__((always_inline)) inline void phi01_tile(int n0, int n1,
 // are expanded), the combinations passing it are queued and tested on r_tc
 // a full wave at a time.  Survivors are ballot-compacted into the wave's
 // chunks of the triplet list with their frame-local indices (tile-local
-// index + tile start a0, a1, a2).  Returns the number of survivors.
+// index + tile start a0, a1, a2).  Returns the number of survivors; those
+// not stored because the list is full are added to `lost`.
 template <int TT>
 __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, int n2, int a0, int a1, int a2,
                                                                const Consts& C, CutLds<TT>& L, const TripList& T,
-                                                               Cursor& cur, int& done,
+                                                               Cursor& cur, int& done, int& lost,
                                                                int32_t* __restrict__ counters) {
   constexpr int W = CutLds<TT>::W;
   const int lane = threadIdx.x;
@@ -393,6 +394,8 @@ __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, in
           *reinterpret_cast<int2*>(T.trips + 2 * slot) = make_int2(f, (int32_t)pack_local(a0 + j0, a1 + j1, a2 + j2));
         }
         cur.used += c;
+      } else {
+        lost += c;   // the list is full: these survivors are not stored
       }
     }
     total += c;
@@ -486,7 +489,8 @@ __device__ __attribute__((always_inline)) inline int cut_tiles(int f, int b0, in
                                                                const float* __restrict__ Y,
                                                                const float* __restrict__ Z, const Consts& C,
                                                                CutLds<TT>& L, const TripList& T, Cursor& cur,
-                                                               int& done, int32_t* __restrict__ counters) {
+                                                               int& done, int& lost,
+                                                               int32_t* __restrict__ counters) {
   constexpr int W = CutLds<TT>::W;
   const int lane = threadIdx.x;
   int total = 0;
@@ -512,7 +516,7 @@ __device__ __attribute__((always_inline)) inline int cut_tiles(int f, int b0, in
         __syncthreads();
         stage_layer(2, b2 + a2, m2);
         __syncthreads();
-        total += join_tile<TT>(f, m1, m2, a0, a1, a2, C, L, T, cur, done, counters);
+        total += join_tile<TT>(f, m1, m2, a0, a1, a2, C, L, T, cur, done, lost, counters);
       }
     }
   }
@@ -553,6 +557,7 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
     return 0;
   }
   int total = 0;   // triplets passing all cuts (exact)
+  int lost = 0;    // of those, not stored (the triplet list was full)
   const int fid = cur.id, fused = cur.used;   // where this frame's entries begin
   if (n0 > 0 && n2 > 0 && n1 > 0) {
     if (n0 <= TT && n1 <= TT && n2 <= TT) {
@@ -576,7 +581,7 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
       __syncthreads();
       phi01_tile<TT>(n0, n1, C, L);
       __syncthreads();
-      total = join_tile<TT>(f, n1, n2, 0, 0, 0, C, L, T, cur, done, counters);
+      total = join_tile<TT>(f, n1, n2, 0, 0, 0, C, L, T, cur, done, lost, counters);
     } else {
       // ---- LDS overflow: the frame is deferred to k_tiles, which runs it
       // tile by tile and writes its flags and triplet count
@@ -587,10 +592,11 @@ __device__ __attribute__((always_inline)) inline int cut_frame(int f, const Fram
   const bool ovf = total > C.max_trip;
   if (lane == 0) {
     counts[3 * f] = total;
-    flags[f] = ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u;
+    flags[f] = (ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u) | (lost ? (MU3E_LIST_FULL | MU3E_KEEP) : 0u);
   }
   // an overflowing frame is rolled back within the current chunk; entries it
-  // left in chunks closed meanwhile are skipped by their frame flag
+  // left in chunks closed meanwhile are skipped by their frame flag (as are
+  // those of a frame the list could not hold)
   if (ovf && cur.id >= 0) cur.used = cur.id == fid ? fused : 0;
   __syncthreads();
   return ovf ? 0 : total;
@@ -682,12 +688,13 @@ k_tiles(const float* __restrict__ X, const float* __restrict__ Y, const float* _
     const int f = defer[k];
     const int b0 = lo[4 * f], b1 = lo[4 * f + 1], b2 = lo[4 * f + 2], b3 = lo[4 * f + 3];
     const int fid = cur.id, fused = cur.used;
-    const int total = cut_tiles<TT>(f, b0, b1, b2, b1 - b0, b2 - b1, b3 - b2, X, Y, Z, C, L, T, cur, done,
+    int lost = 0;
+    const int total = cut_tiles<TT>(f, b0, b1, b2, b1 - b0, b2 - b1, b3 - b2, X, Y, Z, C, L, T, cur, done, lost,
                                     counters);
     const bool ovf = total > C.max_trip;
     if (lane == 0) {
       counts[3 * f] = total;
-      flags[f] = ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u;
+      flags[f] = (ovf ? (MU3E_TRIPLET_OVF | MU3E_KEEP) : 0u) | (lost ? (MU3E_LIST_FULL | MU3E_KEEP) : 0u);
     }
     if (ovf && cur.id >= 0) cur.used = cur.id == fid ? fused : 0;
     selected += ovf ? 0 : total;
@@ -777,6 +784,7 @@ enum { TR_REJECT = 0, TR_ACCEPT = 1, TR_REDO = 2 };
 constexpr int kTrackSlots = 16;
 
 struct TrackOut {
+  uint32_t* flags;   // per-frame flags [F]
   int32_t* res;      // [triplet capacity][4]
   int32_t* redo;     // [redo_cap] entry indices
   int redo_cap;
@@ -809,8 +817,12 @@ __device__ inline void emit_result(bool active, int r, int e, int f, int i3, flo
   if (!active) return;
   if (r < 0) {
     const int q = qbase + rank_below(und);
-    if (q < O.redo_cap) O.redo[q] = e;
-    else atomicOr(&counters[2], ST_TRACK_FULL);
+    if (q < O.redo_cap) {
+      O.redo[q] = e;
+    } else {   // the float64 queue is full: this frame stays undecided, kept
+      atomicOr(&counters[2], ST_TRACK_FULL);
+      atomicOr(&O.flags[f], MU3E_LIST_FULL | MU3E_KEEP);
+    }
     store_result(O.res, e, TR_REDO, 0, 0.f, 0.f);
   } else {
     store_result(O.res, e, r == 1 ? TR_ACCEPT : TR_REJECT, i3, kb, c2);
@@ -963,7 +975,7 @@ k_tracks(const float* __restrict__ X, const float* __restrict__ Y, const float* 
       const uint32_t fl = flags[f];
       const EntryHits h = entry_hits(lo, f, (uint32_t)en.y);
       materialize(fl, h.g0, h.g1, h.g2, h.b3, h.b4);   // one round trip for the flag and the offsets
-      if (!(fl & MU3E_TRIPLET_OVF)) r = fit_entry<float>(X, Y, Z, h, C, i3, kb, c2);
+      if (!(fl & (MU3E_TRIPLET_OVF | MU3E_LIST_FULL))) r = fit_entry<float>(X, Y, Z, h, C, i3, kb, c2);
     }
     emit_result(active, r, e, f, i3, kb, c2, O, counters);
   }
@@ -1471,7 +1483,7 @@ __device__ inline bool vertex_candidate(int f, const Consts& C, const uint32_t* 
                                         const int32_t* __restrict__ counts, const int32_t* __restrict__ ccnt,
                                         int& nt) {
   nt = 0;
-  if (flags[f] & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF | MU3E_TRACK_OVF)) return false;
+  if (flags[f] & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF | MU3E_TRACK_OVF | MU3E_LIST_FULL)) return false;
   nt = counts[3 * f + 1];
   if (nt > C.max_trk) return false;
   const int cc = ccnt[f];
@@ -1487,7 +1499,7 @@ k_vcount(int F, int per, Consts C, uint32_t* __restrict__ flags, const int32_t* 
   int nc = 0, ntot = 0, nbig = 0, unused = 0;
   for (int f = f0 + (int)threadIdx.x; f < f1; f += 256) {
     const uint32_t fl = flags[f];
-    if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF)) && counts[3 * f + 1] > C.max_trk)
+    if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF | MU3E_LIST_FULL)) && counts[3 * f + 1] > C.max_trk)
       flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP;
     int nt;
     if (vertex_candidate(f, C, flags, counts, ccnt, nt)) { ++nc; ntot += nt; nbig += nt > kTrackSlots; }
@@ -1623,7 +1635,11 @@ k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const f
       vertex_wave(f, nt, RangeId{0}, svt, svok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
     } else {
       const int b = vbase[f], n = vpos[f];
-      if (b < 0 || b + n > vcap) continue;   // table full: reported in the status word
+      if (b < 0) continue;
+      if (b + nt > vcap) {   // table full (reported in the status word): the frame is kept unprocessed
+        if (lane == 0) flags[f] |= MU3E_LIST_FULL | MU3E_KEEP;
+        continue;
+      }
       vertex_wave(f, n, RangeId{b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
     }
   }
@@ -1893,8 +1909,9 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   return W;
 }
 
-TrackOut track_out(const WsView& W, int32_t* counts) {
+TrackOut track_out(const WsView& W, uint32_t* flags, int32_t* counts) {
   TrackOut O;
+  O.flags = flags;
   O.res = W.res;
   O.redo = W.redo;
   O.redo_cap = W.redo_cap;
@@ -1936,8 +1953,8 @@ void launch_tiles(const mu3e_hits_t& h, const Consts& C, int cus, int tile, cons
 // the entries not fitted yet, float64 re-evaluation.  after_fits (nullable)
 // is recorded after k_tracks.
 void launch_tracks(const mu3e_hits_t& h, const Consts& C, int cus, const WsView& W, const TripList& T,
-                   const uint32_t* flags, int32_t* counts, hipStream_t stream, hipEvent_t after_fits) {
-  const TrackOut O = track_out(W, counts);
+                   uint32_t* flags, int32_t* counts, hipStream_t stream, hipEvent_t after_fits) {
+  const TrackOut O = track_out(W, flags, counts);
   const int nbk = (int)(((int64_t)T.capacity / T.chunk + 1 + 255) / 256);
   hipLaunchKernelGGL(k_scount, dim3(nbk), dim3(256), 0, stream, T, W.sblk, W.counters, W.claims);
   hipLaunchKernelGGL(k_splace, dim3(nbk), dim3(256), 0, stream, T, W.S, W.sblk, W.counters);
@@ -2294,7 +2311,7 @@ static void part_launch(const mu3e_plan& pl, const PlanPart& q, int stage, hipSt
     hipLaunchKernelGGL(k_init, dim3(kClaimRanges), dim3(256), 0, s, q.W.counters, q.T.pre * q.T.chunk, q.W.claims);
     if (q.F == 0) return;
     if (ev) (void)hipEventRecord(ev[0], s);
-    const TrackOut O = track_out(q.W, q.counts);
+    const TrackOut O = track_out(q.W, q.flags, q.counts);
     hipLaunchKernelGGL(batched_kernel(pl.tuning.fuse_fits != 0, pl.tuning.tile_hits), dim3(q.P), dim3(kWave), 0, s,
                        h.x, h.y, h.z, h.layer_offsets, q.F, q.Fs, h.n_hits, pl.C, q.flags, q.counts, q.vertex,
                        q.W.ccnt, q.T, O, q.W.counters, q.W.claims, pl.tuning.frames_per_claim, q.W.defer);

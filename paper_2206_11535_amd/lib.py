@@ -15,7 +15,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmu3e.so")
 
-KEEP, TRIPLET_OVF, TRACK_OVF, COMBO_OVF, VERTEX, HITS_OVF = 1, 2, 4, 8, 16, 32
+KEEP, TRIPLET_OVF, TRACK_OVF, COMBO_OVF, VERTEX, HITS_OVF, LIST_FULL = 1, 2, 4, 8, 16, 32, 64
 MAX_LAYER_HITS = 128
 STATUS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "workspace too small",
           -4: "unsupported parameter"}

@@ -431,13 +431,19 @@ def test_triplet_list_full(lib, cap):
     b = lib.BatchedSelector(dh, p, triplet_capacity=cap, waves_per_cu=4, frames_per_claim=2, steal_percent=25)
     b.run()
     torch.cuda.synchronize()
-    _, cr, _ = ref.result()
+    fr, cr, vr = ref.result()
     assert ref.counters()[2] == 0
     for sel in (a, b):
         c = sel.counters()
         assert c[2] & 1, c
-        _, cs, _ = sel.result()
+        fs_, cs, vs = sel.result()
         assert np.array_equal(cs[:, 0], cr[:, 0])
+        # every frame whose triplets the list could not hold is flagged and
+        # kept; every other frame is processed fully, as with a large list
+        full = (fs_ & lib.LIST_FULL) != 0
+        assert full.any() and np.all(fs_[full] & lib.KEEP) and np.all(cs[full, 0] > 0)
+        assert np.array_equal(fs_[~full], fr[~full]) and np.array_equal(cs[~full], cr[~full])
+        assert np.array_equal(np.nan_to_num(vs[~full]), np.nan_to_num(vr[~full]))
     # the plan runs again, still reporting the full list
     b.run()
     torch.cuda.synchronize()
