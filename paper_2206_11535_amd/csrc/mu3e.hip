@@ -779,9 +779,13 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
 enum { TR_REJECT = 0, TR_ACCEPT = 1, TR_REDO = 2 };
 
 // Accepted tracks per frame also note their entry index in the frame's row of
-// tslot (the first kTrackSlots of them), so that the vertex stage finds the
-// tracks of its candidate frames without scanning the list.
-constexpr int kTrackSlots = 16;
+// tslot (the first nslot of them), so that the vertex stage finds the tracks
+// of its candidate frames without scanning the list.  nslot follows the
+// track capacity per frame the caller asks for (track_slots); frames with at
+// most kSmallSlots tracks are refitted into LDS by the vertex wave, larger
+// ones into their slice of the workspace's track table.
+constexpr int kSmallSlots = 16;
+constexpr int kMaxSlots = 128;
 
 struct TrackOut {
   uint32_t* flags;   // per-frame flags [F]
@@ -790,7 +794,8 @@ struct TrackOut {
   int redo_cap;
   int32_t* counts;   // per-frame counts [3F]; tracks at 3f + 1
   int32_t* ccnt;     // per-frame charge tally: +1 per e+, +65536 per e-
-  int32_t* tslot;    // [F][kTrackSlots] entry indices of accepted tracks
+  int32_t* tslot;    // [F][nslot] entry indices of accepted tracks
+  int nslot;
 };
 
 __device__ inline void store_result(int32_t* __restrict__ res, int e, int code, int i3, float kb, float c2) {
@@ -799,7 +804,7 @@ __device__ inline void store_result(int32_t* __restrict__ res, int e, int code, 
 
 __device__ inline void tally_track(const TrackOut& O, int f, int e, float kb) {
   const int rank = atomicAdd(&O.counts[3 * f + 1], 1);
-  if (rank < kTrackSlots) O.tslot[f * kTrackSlots + rank] = e;
+  if (rank < O.nslot) O.tslot[f * O.nslot + rank] = e;
   atomicAdd(&O.ccnt[f], kb > 0.f ? 1 : 65536);
 }
 
@@ -1280,17 +1285,12 @@ __device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* 
 
 constexpr int kVtxTracks = 256;   // tracks of one frame staged in LDS for the vertex wave
 
-__device__ inline int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // Vertex stage of one frame by one wave (Alg. 4): tracks split by charge,
-// lanes over the flat index of e+e+e- triples (unordered e+ pair, e-);
-// first the energy test and the combination cap, then the vertex estimate of
-// every energy-passing triple and a wave-wide minimum of the vertex chi2
-// (ties to the lowest triple index).  id(j) gives the j-th track slot.
+// lanes over the flat index of e+e+e- triples (unordered e+ pair, e-) for
+// the energy test and the combination cap; the energy-passing triples are
+// compacted so that the vertex estimate runs on full waves; a wave-wide
+// minimum of the vertex chi2 (ties to the lowest triple index) gives the
+// reported vertex.  id(j) gives the j-th track slot.
 // Optional record of the energy-passing triples of a frame (debug view of
 // the standalone vertex entry point): rows {frame, track a, track b, track c}
 // (a, b the e+ tracks, c the e- track, as given by id) appended to rows[cap]
@@ -1305,7 +1305,6 @@ template <class Id>
 __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict__ vt,
                             const int32_t* __restrict__ vok, const Consts& C, uint32_t* __restrict__ flags,
                             int32_t* __restrict__ ncombo, float* __restrict__ vtx, TripleRec rec = TripleRec{}) {
-  __shared__ int spos[kVtxTracks], sneg[kVtxTracks];
   const int lane = threadIdx.x;
   const double elo = kMassMu - (double)C.de_max, ehi = kMassMu + (double)C.de_max;
   if (n > kVtxTracks) {
@@ -1349,7 +1348,10 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     }
     return;
   }
-  // ---- split by charge (ballot compaction)
+  // ---- split by charge (ballot compaction): the e+ tracks from the front
+  // of sid, the e- tracks from its back; their energies alongside in sE
+  __shared__ int sid[kVtxTracks];
+  __shared__ double sE[kVtxTracks];
   int np = 0, nn = 0;
   for (int base = 0; base < n; base += kWave) {
     const int j = base + lane;
@@ -1357,104 +1359,128 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     const bool ok = t >= 0 && vok[t];
     const bool ps = ok && vt[t].q > 0, ng = ok && vt[t].q < 0;
     const unsigned long long mp = ballot(ps), mn = ballot(ng);
-    if (ps) spos[np + rank_below(mp)] = t;
-    if (ng) sneg[nn + rank_below(mn)] = t;
+    if (ps) { const int k = np + rank_below(mp); sid[k] = t; sE[k] = vt[t].E; }
+    if (ng) { const int k = kVtxTracks - 1 - (nn + rank_below(mn)); sid[k] = t; sE[k] = vt[t].E; }
     np += __popcll(mp);
     nn += __popcll(mn);
   }
   __syncthreads();
   const int npair = np * (np - 1) / 2;
-  const int total = npair * nn;
-  auto decode = [&](int k, int& ta, int& tb, int& te) {
-    int q = k / nn;
-    te = sneg[k - q * nn];
-    int i = 0;
-    while (q >= np - 1 - i) { q -= np - 1 - i; ++i; }
-    ta = spos[i];
-    tb = spos[i + 1 + q];
+  const int total = npair * nn;   // n <= 256 tracks: below 2^23
+  // flat triple index k -> (e+ i, e+ j > i, e- e): k = pair * nn + e, pairs in
+  // row-major order (row i holds np - 1 - i pairs and starts at
+  // i (2 np - i - 1) / 2), the row found by the quadratic formula and corrected
+  auto decode = [&](int k, int& i, int& j, int& e) {
+    const int q = (int)(((double)k + 0.5) / (double)nn);
+    e = k - q * nn;
+    const double b = 2.0 * np - 1.0;
+    int r = (int)((b - sqrt(fmax(b * b - 8.0 * q, 0.0))) * 0.5);
+    r = r < 0 ? 0 : (r > np - 2 ? np - 2 : r);
+    while (r > 0 && r * (2 * np - r - 1) / 2 > q) --r;
+    while (r + 1 <= np - 2 && (r + 1) * (2 * np - r - 2) / 2 <= q) ++r;
+    i = r;
+    j = q - r * (2 * np - r - 1) / 2 + r + 1;
   };
-  // ---- energy test over all triples, combination cap
-  int cnt = 0;
+  // ---- energy test over every triple (the count is exact even above the
+  // cap), and while the count stays within the cap, the passing triples are
+  // ballot-compacted into an LDS queue whose full waves get the vertex
+  // estimate: per triple its intersection points (one lane each), then the
+  // existing (triple, combination) pairs a full wave at a time.  The result
+  // is the passing combination with the lowest chi2, ties to the lowest
+  // (triple index, combination).
+  __shared__ VPoints sP[kWave];
+  __shared__ int sT[3 * kWave];
+  __shared__ int sq[8 * kWave];
+  __shared__ int sk[2 * kWave];   // queue of energy-passing triple indices
+  __shared__ int skey[kWave];     // the triple index of each lane's points in sP
+  double best = 1e300;
+  long long bestk = 0x7fffffffffffffffLL;
+  double bv[3] = {0, 0, 0};
+  auto estimate = [&](int m) {   // the first m (<= kWave) queued triples
+    int ta = 0, tb = 0, te = 0, k = 0;
+    int mc = 0;
+    if (lane < m) {
+      k = sk[lane];
+      int i, j, e;
+      decode(k, i, j, e);
+      ta = sid[i]; tb = sid[j]; te = sid[kVtxTracks - 1 - e];
+      VPoints P;
+      if (vertex_points(&vt[ta], &vt[tb], &vt[te], C, P)) {
+        mc = vertex_combos(P);
+        sP[lane] = P;
+      }
+    }
+    sT[3 * lane] = ta; sT[3 * lane + 1] = tb; sT[3 * lane + 2] = te;
+    skey[lane] = k;   // for the tie-break key
+    const int nc = __popc((unsigned)mc);   // <= 8
+    int pos = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+      const unsigned long long mb = ballot((nc >> bit) & 1);
+      pos += rank_below(mb) << bit;
+      tot += __popcll(mb) << bit;
+    }
+    for (int c = 0; c < 8; ++c)
+      if (mc >> c & 1) sq[pos++] = lane * 8 + c;
+    __syncthreads();
+    for (int q0 = 0; q0 < tot; q0 += kWave) {
+      if (q0 + lane < tot) {
+        const int ec = sq[q0 + lane];
+        const int l = ec >> 3, c = ec & 7;
+        double u[4];
+        if (vertex_combo(&vt[sT[3 * l]], &vt[sT[3 * l + 1]], &vt[sT[3 * l + 2]], C, sP[l], c, u)) {
+          const long long key = (long long)skey[l] * 8 + c;
+          if (u[3] < best || (u[3] == best && key < bestk)) {
+            best = u[3]; bestk = key; bv[0] = u[0]; bv[1] = u[1]; bv[2] = u[2];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  };
+  int cnt = 0, nq = 0;
   for (int base = 0; base < total; base += kWave) {
     const int k = base + lane;
-    int ta = 0, tb = 0, te = 0;
+    int i = 0, j = 0, e = 0;
     bool ep = false;
     if (k < total) {
-      decode(k, ta, tb, te);
-      const double s = vt[ta].E + vt[tb].E + vt[te].E;
+      decode(k, i, j, e);
+      const double s = sE[i] + sE[j] + sE[kVtxTracks - 1 - e];
       ep = s >= elo && s <= ehi;
     }
-    cnt += ep;
+    const unsigned long long bm = ballot(ep);
+    if (bm == 0ull) continue;   // wave-uniform
+    const int c = __popcll(bm);
     if (rec.rows) {   // debug record (wave-uniform pointer)
-      const unsigned long long bm = ballot(ep);
       int r0 = 0;
-      if (bm != 0ull && lane == 0) r0 = atomicAdd(rec.n, __popcll(bm));
+      if (lane == 0) r0 = atomicAdd(rec.n, c);
       r0 = lane_value(r0, 0);
       const int r = r0 + rank_below(bm);
-      if (ep && r < rec.cap) *reinterpret_cast<int4*>(rec.rows + 4 * r) = make_int4(f, ta, tb, te);
+      if (ep && r < rec.cap)
+        *reinterpret_cast<int4*>(rec.rows + 4 * r) = make_int4(f, sid[i], sid[j], sid[kVtxTracks - 1 - e]);
+    }
+    cnt += c;
+    if (cnt > C.max_combo) continue;   // over the cap: only counted from here on
+    if (ep) sk[nq + rank_below(bm)] = k;
+    nq += c;
+    if (nq >= kWave) {
+      __syncthreads();
+      estimate(kWave);
+      const int rem = nq - kWave;
+      const int v = lane < rem ? sk[kWave + lane] : 0;
+      __syncthreads();
+      if (lane < rem) sk[lane] = v;
+      __syncthreads();
+      nq = rem;
     }
   }
-  cnt = wave_sum(cnt);
   if (lane == 0) *ncombo = cnt;
   if (cnt > C.max_combo) {
     if (lane == 0) *flags |= MU3E_COMBO_OVF | MU3E_KEEP;
     __syncthreads();
     return;
   }
-  // ---- vertex of every energy-passing triple.  Per round of kWave triples:
-  // each lane finds the intersection points of one triple (into LDS), then
-  // the existing (triple, combination) pairs are evaluated a full wave at a
-  // time.  The result is the passing combination with the lowest chi2, ties
-  // to the lowest (triple index, combination).
-  __shared__ VPoints sP[kWave];
-  __shared__ int sT[3 * kWave];
-  __shared__ int sq[8 * kWave];
-  double best = 1e300;
-  long long bestk = 0x7fffffffffffffffLL;
-  double bv[3] = {0, 0, 0};
-  if (cnt > 0) {
-    for (int base = 0; base < total; base += kWave) {
-      const int k = base + lane;
-      int ta = 0, tb = 0, te = 0;
-      bool ep = false;
-      if (k < total) {
-        decode(k, ta, tb, te);
-        const double s = vt[ta].E + vt[tb].E + vt[te].E;
-        ep = s >= elo && s <= ehi;
-      }
-      if (ballot(ep) == 0ull) continue;   // wave-uniform
-      VPoints P;
-      int m = 0;
-      if (ep && vertex_points(&vt[ta], &vt[tb], &vt[te], C, P)) m = vertex_combos(P);
-      if (m) sP[lane] = P;
-      sT[3 * lane] = ta; sT[3 * lane + 1] = tb; sT[3 * lane + 2] = te;
-      const int nc = __popc((unsigned)m);   // <= 8
-      int pos = 0, tot = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const unsigned long long mb = ballot((nc >> b) & 1);
-        pos += rank_below(mb) << b;
-        tot += __popcll(mb) << b;
-      }
-      for (int c = 0; c < 8; ++c)
-        if (m >> c & 1) sq[pos++] = lane * 8 + c;
-      __syncthreads();
-      for (int q0 = 0; q0 < tot; q0 += kWave) {
-        if (q0 + lane < tot) {
-          const int e = sq[q0 + lane];
-          const int l = e >> 3, c = e & 7;
-          double u[4];
-          if (vertex_combo(&vt[sT[3 * l]], &vt[sT[3 * l + 1]], &vt[sT[3 * l + 2]], C, sP[l], c, u)) {
-            const long long key = (long long)(base + l) * 8 + c;
-            if (u[3] < best || (u[3] == best && key < bestk)) {
-              best = u[3]; bestk = key; bv[0] = u[0]; bv[1] = u[1]; bv[2] = u[2];
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  if (nq > 0) { __syncthreads(); estimate(nq); }
   // wave-wide minimum of (chi2, key)
   double wb = best;
   long long wk = bestk;
@@ -1493,7 +1519,7 @@ __device__ inline bool vertex_candidate(int f, const Consts& C, const uint32_t* 
 
 __global__ void __launch_bounds__(256)
 k_vcount(int F, int per, Consts C, uint32_t* __restrict__ flags, const int32_t* __restrict__ counts,
-         const int32_t* __restrict__ ccnt, int32_t* __restrict__ blk) {
+         const int32_t* __restrict__ ccnt, int32_t* __restrict__ blk, int nslot) {
   __shared__ int tmp[512];
   const int f0 = blockIdx.x * per, f1 = min(F, f0 + per);
   int nc = 0, ntot = 0, nbig = 0, unused = 0;
@@ -1502,7 +1528,7 @@ k_vcount(int F, int per, Consts C, uint32_t* __restrict__ flags, const int32_t* 
     if (!(fl & (MU3E_HITS_OVF | MU3E_TRIPLET_OVF | MU3E_LIST_FULL)) && counts[3 * f + 1] > C.max_trk)
       flags[f] = fl | MU3E_TRACK_OVF | MU3E_KEEP;
     int nt;
-    if (vertex_candidate(f, C, flags, counts, ccnt, nt)) { ++nc; ntot += nt; nbig += nt > kTrackSlots; }
+    if (vertex_candidate(f, C, flags, counts, ccnt, nt)) { ++nc; ntot += nt; nbig += nt > nslot; }
   }
   block_sum2(nc, ntot, tmp);
   block_sum2(nbig, unused, tmp);
@@ -1577,7 +1603,7 @@ __global__ void __launch_bounds__(64)
 k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
         const int32_t* __restrict__ lo, Consts C, TripList T, Slices S, const int32_t* __restrict__ res,
         const int32_t* __restrict__ counts, const int32_t* __restrict__ counters, const int32_t* __restrict__ vbase,
-        int32_t* __restrict__ vpos, int vcap, VTrack* __restrict__ vt, int32_t* __restrict__ vok) {
+        int32_t* __restrict__ vpos, int vcap, VTrack* __restrict__ vt, int32_t* __restrict__ vok, int nslot) {
   if (counters[11] == 0) return;   // every candidate frame's tracks are in its slot row
   const int ns = counters[10];
   for (int v = blockIdx.x; v < ns; v += gridDim.x) {
@@ -1587,7 +1613,7 @@ k_vprep(const float* __restrict__ X, const float* __restrict__ Y, const float* _
     if (res[4 * e] != TR_ACCEPT) continue;
     const int f = T.trips[2 * e];
     const int b = vbase[f];
-    if (b < 0 || counts[3 * f + 1] <= kTrackSlots) continue;
+    if (b < 0 || counts[3 * f + 1] <= nslot) continue;
     const int pos = atomicAdd(&vpos[f], 1);
     if (b + pos >= vcap) continue;   // table full: reported by k_vplace
     const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
@@ -1602,46 +1628,60 @@ struct RangeId {
   __device__ int operator()(int j) const { return base + j; }
 };
 
-// One wave per candidate frame.  A frame with at most kTrackSlots tracks
-// refits them here (lanes over its slot row) into LDS; a larger one uses the
-// table slice filled by k_vprep.  Each frame is a long chain of dependent
-// float64 work on few lanes, so two waves per SIMD (at most 256 registers,
-// a few spilled) beat one wave with every value in registers.
+// One wave per candidate frame.  A frame with at most kSmallSlots tracks
+// refits them here (lanes over its slot row) into LDS; one with at most
+// nslot into its slice of the track table; a larger one uses the table slice
+// filled by k_vprep.  Each frame is a long chain of dependent float64 work,
+// so two waves per SIMD (at most 256 registers, a few spilled) beat one wave
+// with every value in registers.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
                const int32_t* __restrict__ lo, Consts C, TripList T, const int32_t* __restrict__ res,
-               const int32_t* __restrict__ tslot, const int32_t* __restrict__ counters,
+               const int32_t* __restrict__ tslot, int nslot, const int32_t* __restrict__ counters,
                const int32_t* __restrict__ cand, const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos,
-               int vcap, const VTrack* __restrict__ vt, const int32_t* __restrict__ vok,
-               uint32_t* __restrict__ flags, int32_t* __restrict__ counts, float* __restrict__ vtx) {
-  __shared__ VTrack svt[kTrackSlots];
-  __shared__ int32_t svok[kTrackSlots];
+               int vcap, VTrack* __restrict__ vt, int32_t* __restrict__ vok, uint32_t* __restrict__ flags,
+               int32_t* __restrict__ counts, float* __restrict__ vtx) {
+  __shared__ VTrack svt[kSmallSlots];
+  __shared__ int32_t svok[kSmallSlots];
   const int lane = threadIdx.x;
   const int nc = counters[3];
+  // refit of the tracks of frame f's slot row: lane j takes slot j (j < nt)
+  auto refit = [&](int f, int j, VTrack& v) -> bool {
+    const int e = tslot[f * nslot + j];
+    const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
+    const EntryHits eh = entry_hits(lo, f, pk);
+    const int32_t h[4] = {eh.g0, eh.g1, eh.g2, eh.b3 + res[4 * e + 1]};
+    return vtrack_make(X, Y, Z, n_hits, h, C, v);
+  };
   for (int c = blockIdx.x; c < nc; c += gridDim.x) {
     const int f = cand[c];
     const int nt = counts[3 * f + 1];
-    if (nt <= kTrackSlots) {
+    if (nt <= kSmallSlots) {
       if (lane < nt) {
-        const int e = tslot[f * kTrackSlots + lane];
-        const uint32_t pk = (uint32_t)T.trips[2 * e + 1];
-        const EntryHits eh = entry_hits(lo, f, pk);
-        const int32_t h[4] = {eh.g0, eh.g1, eh.g2, eh.b3 + res[4 * e + 1]};
         VTrack v;
-        svok[lane] = vtrack_make(X, Y, Z, n_hits, h, C, v) ? 1 : 0;
+        svok[lane] = refit(f, lane, v) ? 1 : 0;
         svt[lane] = v;
       }
       __syncthreads();
       vertex_wave(f, nt, RangeId{0}, svt, svok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
-    } else {
-      const int b = vbase[f], n = vpos[f];
-      if (b < 0) continue;
-      if (b + nt > vcap) {   // table full (reported in the status word): the frame is kept unprocessed
-        if (lane == 0) flags[f] |= MU3E_LIST_FULL | MU3E_KEEP;
-        continue;
-      }
-      vertex_wave(f, n, RangeId{b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
+      continue;
     }
+    const int b = vbase[f];
+    if (b < 0) continue;
+    if (b + nt > vcap) {   // table full (reported in the status word): the frame is kept unprocessed
+      if (lane == 0) flags[f] |= MU3E_LIST_FULL | MU3E_KEEP;
+      continue;
+    }
+    if (nt <= nslot) {   // refitted here; otherwise k_vprep filled the slice
+      for (int j = lane; j < nt; j += kWave) {
+        VTrack v;
+        vok[b + j] = refit(f, j, v) ? 1 : 0;
+        vt[b + j] = v;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    vertex_wave(f, nt <= nslot ? nt : vpos[f], RangeId{b}, vt, vok, C, &flags[f], &counts[3 * f + 2], vtx + 4 * f);
   }
 }
 
@@ -1811,7 +1851,17 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t counters, claims, chunks, trips, res, sfit, sall, sblk, redo, vt, vok, ccnt, vbase, vpos, cand, vblk, tslot,
       defer, total;
+  int nslot;
 };
+
+// Track slots per frame: the track capacity per frame the caller provides,
+// rounded up to a power of two, within [kSmallSlots, kMaxSlots].
+inline int track_slots(int64_t F, int64_t kc) {
+  const int64_t per = F > 0 ? (kc + F - 1) / F : 0;
+  int n = kSmallSlots;
+  while (n < per && n < kMaxSlots) n *= 2;
+  return n;
+}
 
 // Entries of each slice table: at most ceil(count / 64) slices per chunk.
 inline int64_t slice_capacity(int64_t tc) { return tc / kWave + tc / kMinChunk + 2; }
@@ -1835,7 +1885,8 @@ Layout layout(int64_t F, int64_t tc, int64_t kc) {
   L.vpos = o; o += align256((size_t)F * sizeof(int32_t));
   L.cand = o; o += align256((size_t)F * sizeof(int32_t));
   L.vblk = o; o += align256((size_t)3 * kVBlocks * sizeof(int32_t));
-  L.tslot = o; o += align256((size_t)F * kTrackSlots * sizeof(int32_t));
+  L.nslot = track_slots(F, kc);
+  L.tslot = o; o += align256((size_t)F * L.nslot * sizeof(int32_t));
   L.defer = o; o += align256((size_t)F * sizeof(int32_t));
   L.total = o;
   return L;
@@ -1881,7 +1932,7 @@ struct WsView {
       *defer;
   Slices S;
   VTrack* vt;
-  int redo_cap;
+  int redo_cap, nslot;
 };
 
 WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
@@ -1904,6 +1955,7 @@ WsView ws_view(void* workspace, const Layout& L, int track_capacity) {
   W.cand = reinterpret_cast<int32_t*>(ws + L.cand);
   W.vblk = reinterpret_cast<int32_t*>(ws + L.vblk);
   W.tslot = reinterpret_cast<int32_t*>(ws + L.tslot);
+  W.nslot = L.nslot;
   W.defer = reinterpret_cast<int32_t*>(ws + L.defer);
   W.redo_cap = track_capacity / 8 + 1024;
   return W;
@@ -1918,6 +1970,7 @@ TrackOut track_out(const WsView& W, uint32_t* flags, int32_t* counts) {
   O.counts = counts;
   O.ccnt = W.ccnt;
   O.tslot = W.tslot;
+  O.nslot = W.nslot;
   return O;
 }
 
@@ -1976,17 +2029,17 @@ void launch_vertex(const mu3e_hits_t& h, const Consts& C, int F, int cus, const 
   if (nb > kVBlocks) nb = kVBlocks;
   const int per = ((F + nb - 1) / nb + 255) / 256 * 256;
   nb = (F + per - 1) / per;
-  hipLaunchKernelGGL(k_vcount, dim3(nb), dim3(256), 0, stream, F, per, C, flags, counts, W.ccnt, W.vblk);
+  hipLaunchKernelGGL(k_vcount, dim3(nb), dim3(256), 0, stream, F, per, C, flags, counts, W.ccnt, W.vblk, W.nslot);
   hipLaunchKernelGGL(k_vplace, dim3(nb), dim3(256), 0, stream, F, per, C, flags, counts, W.ccnt, W.vblk, W.vbase,
                      W.vpos, W.cand, vcap, W.counters);
   hipLaunchKernelGGL(k_vprep, dim3(cus * 16), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets, C, T,
-                     W.S, W.res, counts, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok);
+                     W.S, W.res, counts, W.counters, W.vbase, W.vpos, vcap, W.vt, W.vok, W.nslot);
   if (ev) (void)hipEventRecord(ev[3], stream);
   // two waves per SIMD are resident (float64-heavy, many registers): no
   // more blocks than that, so that every candidate frame starts at once
   hipLaunchKernelGGL(k_vframes_list, dim3(cus * 8), dim3(kWave), 0, stream, h.x, h.y, h.z, h.n_hits, h.layer_offsets,
-                     C, T, W.res, W.tslot, W.counters, W.cand, W.vbase, W.vpos, vcap, W.vt, W.vok, flags, counts,
-                     vtx);
+                     C, T, W.res, W.tslot, W.nslot, W.counters, W.cand, W.vbase, W.vpos, vcap, W.vt, W.vok, flags,
+                     counts, vtx);
   if (ev) (void)hipEventRecord(ev[4], stream);
 }
 
