@@ -277,6 +277,31 @@ mu3e_status mu3e_vertex_debug(const mu3e_hits_t *hits, const mu3e_tracks_t *trac
                               size_t workspace_bytes, int32_t *triples, int32_t triple_capacity,
                               int32_t *n_triples, hipStream_t stream);
 
+/* ---- Chunk ingest (Section V-A) ------------------------------------------
+ * A chunk is a fixed-size buffer written by the readout and copied to the
+ * GPU as is (from pinned host memory, one stream per chunk in flight):
+ *   bytes [0, 12 n)                 n hit records {float x, y, z} (mm), sorted
+ *                                   by frame and then layer
+ *   int32 [4F+1] just before the    layer offsets: frame f, layer l owns
+ *   last four bytes                 records [off[4f+l], off[4f+l+1]); off[0] = 0,
+ *                                   off[4F] = n
+ *   int32, the last four bytes      F, the number of frames in the chunk
+ * The space between the records and the offsets is unused.  The tail is
+ * read from byte (chunk_bytes & ~3) - 4 backwards. */
+
+/* Unpacks a chunk (device pointer, 4-byte aligned, chunk_bytes long) into SoA
+ * hits x, y, z [max_hits] and layer_offsets [4*max_frames+1] (device
+ * buffers owned by the caller), padding frames F .. max_frames-1 as empty so
+ * that a selection or a plan bound to max_frames frames and max_hits hits
+ * runs any chunk.  info [2] (device) receives {F, n}; a chunk whose tail is
+ * inconsistent (F < 0 or > max_frames, offsets overlapping the records,
+ * off[0] != 0, n > max_hits) yields {-1, -1} and no frames (all offsets 0).
+ * Offsets that decrease inside a consistent tail are passed on: the
+ * selection skips such frames and reports them (status bit 4). */
+mu3e_status mu3e_chunk_unpack(const void *chunk, int64_t chunk_bytes, int32_t max_frames,
+                              int32_t max_hits, float *x, float *y, float *z,
+                              int32_t *layer_offsets, int32_t *info, hipStream_t stream);
+
 /* ---- Batched form ------------------------------------------------------
  * A plan captures the whole selection of one batch of frames into a HIP
  * graph around one persistent kernel: waves take the frames of the batch

@@ -1720,6 +1720,57 @@ k_vframes_range(int F, int n_tracks, Consts C, const int32_t* __restrict__ off, 
   }
 }
 
+// ================================================================ chunks
+// Ingest of a chunk as the readout writes it (Section V-A): hit records of
+// three float32 (x, y, z) from the front, sorted by frame and layer; at the
+// tail the frame count F (last int32) and, just before it, the 4F + 1 layer
+// offsets (hit indices within the chunk).  k_unpack turns it into the SoA
+// hits and layer offsets the selection reads, padding frames F .. max_frames
+// - 1 as empty, so that a plan bound to max_frames frames runs any chunk.  A
+// chunk whose tail is inconsistent (F out of range, offsets overlapping the
+// hit records, more hits than max_hits) yields no frames and info = {-1, -1}.
+struct ChunkTail {
+  int F, n;
+  bool ok;
+};
+
+__device__ inline ChunkTail chunk_tail(const unsigned char* __restrict__ chunk, long long bytes, int max_frames,
+                                       int max_hits) {
+  ChunkTail t{0, 0, false};
+  if (bytes < 4) return t;
+  const int32_t* tail = reinterpret_cast<const int32_t*>(chunk + (bytes & ~3LL) - 4);
+  const int F = tail[0];
+  if (F < 0 || F > max_frames) return t;
+  const long long obytes = 4LL * (4LL * F + 1);
+  if (obytes + 4 > (bytes & ~3LL)) return t;
+  const int32_t* off = tail - (4 * F + 1);
+  const int n = off[4 * F];
+  if (n < 0 || n > max_hits || 12LL * n > (bytes & ~3LL) - 4 - obytes || off[0] != 0) return t;
+  t.F = F;
+  t.n = n;
+  t.ok = true;
+  return t;
+}
+
+__global__ void __launch_bounds__(256)
+k_unpack(const unsigned char* __restrict__ chunk, long long bytes, int max_frames, int max_hits, float* __restrict__ X,
+         float* __restrict__ Y, float* __restrict__ Z, int32_t* __restrict__ lo, int32_t* __restrict__ info) {
+  const ChunkTail t = chunk_tail(chunk, bytes, max_frames, max_hits);
+  const int32_t* off = reinterpret_cast<const int32_t*>(chunk + (bytes & ~3LL) - 4) - (4 * t.F + 1);
+  const float* rec = reinterpret_cast<const float*>(chunk);
+  const int stride = gridDim.x * blockDim.x;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) { info[0] = t.ok ? t.F : -1; info[1] = t.ok ? t.n : -1; }
+  const int nl = 4 * max_frames + 1;
+  for (int j = i0; j < nl; j += stride) lo[j] = !t.ok ? 0 : (j <= 4 * t.F ? off[j] : t.n);
+  if (!t.ok) return;
+  for (int i = i0; i < t.n; i += stride) {
+    X[i] = rec[3 * i];
+    Y[i] = rec[3 * i + 1];
+    Z[i] = rec[3 * i + 2];
+  }
+}
+
 // ================================================================== k_fit
 __global__ void __launch_bounds__(256)
 k_fit(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
@@ -2171,6 +2222,20 @@ mu3e_status mu3e_select_frames_static(const mu3e_hits_t* hits, const mu3e_params
   if (st != MU3E_OK) return st;
   return select_impl(hits, params, frame_flags, frame_counts, frame_vertex, ws, sizeof(scratch), triplet_capacity,
                      track_capacity, dbg, stream, nullptr);
+}
+
+mu3e_status mu3e_chunk_unpack(const void* chunk, int64_t chunk_bytes, int32_t max_frames, int32_t max_hits, float* x,
+                              float* y, float* z, int32_t* layer_offsets, int32_t* info, hipStream_t stream) {
+  if (!chunk || chunk_bytes < 4 || max_frames < 0 || max_hits < 0 || !layer_offsets || !info ||
+      (max_hits > 0 && (!x || !y || !z)) || (reinterpret_cast<uintptr_t>(chunk) & 3))
+    return MU3E_ERR_INVALID_ARG;
+  const int cus = device_cus();
+  const int64_t work = (int64_t)max_hits > 4 * (int64_t)max_frames + 1 ? max_hits : 4 * (int64_t)max_frames + 1;
+  const int blocks = (int)((work + 255) / 256 < cus * 8 ? (work + 255) / 256 : cus * 8);
+  hipLaunchKernelGGL(k_unpack, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, stream,
+                     static_cast<const unsigned char*>(chunk), (long long)chunk_bytes, max_frames, max_hits, x, y, z,
+                     layer_offsets, info);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
 mu3e_status mu3e_fit_triplets(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const mu3e_params_t* params,

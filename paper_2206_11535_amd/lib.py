@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH):
     L.mu3e_select_frames_static.restype = ctypes.c_int
     L.mu3e_select_frames_static.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Params), P, P, P, I, I,
                                             ctypes.POINTER(Debug), P]
+    L.mu3e_chunk_unpack.restype = ctypes.c_int
+    L.mu3e_chunk_unpack.argtypes = [P, ctypes.c_int64, I, I, P, P, P, P, P, P]
     L.mu3e_fit_triplets.restype = ctypes.c_int
     L.mu3e_fit_triplets.argtypes = [ctypes.POINTER(Hits), P, I, ctypes.POINTER(Params), P, P]
     L.mu3e_fit_triplets_backward.restype = ctypes.c_int
@@ -373,6 +375,120 @@ class BatchedSelector(Selector):
         if plan is not None and _lib is not None:
             _lib.mu3e_plan_destroy(plan)
             self.plan = None
+
+
+# ------------------------------------------------------------ chunk ingest
+def chunk_capacity(chunk_bytes: int, max_frames: int) -> int:
+    """Most hit records a chunk of chunk_bytes holds with max_frames frames."""
+    return max(0, (int(chunk_bytes) // 4 * 4 - 4 - 4 * (4 * int(max_frames) + 1)) // 12)
+
+
+def pack_chunk(fs, f0: int, f1: int, out: np.ndarray) -> int:
+    """Writes frames [f0, f1) of a host FrameSet into the chunk buffer `out`
+    (uint8, as the readout would: records {x, y, z} float32 from the front,
+    the layer offsets and the frame count at the tail; see mu3e.h).  Returns
+    the number of hits written; raises if the frames do not fit."""
+    lo = np.asarray(fs.layer_offsets)
+    h0, h1 = int(lo[4 * f0]), int(lo[4 * f1])
+    F, n = f1 - f0, h1 - h0
+    nb = len(out) // 4 * 4
+    tail = 4 + 4 * (4 * F + 1)
+    if 12 * n + tail > nb:
+        raise ValueError(f"{F} frames with {n} hits need {12 * n + tail} bytes; the chunk has {nb}")
+    rec = out[:12 * n].view(np.float32).reshape(n, 3)
+    rec[:, 0] = fs.x[h0:h1]
+    rec[:, 1] = fs.y[h0:h1]
+    rec[:, 2] = fs.z[h0:h1]
+    t = out[nb - tail:nb].view(np.int32)
+    t[:-1] = lo[4 * f0:4 * f1 + 1] - h0
+    t[-1] = F
+    return n
+
+
+class ChunkStream:
+    """Chunk ingest with overlapped copies (Sections V-A, V-B): n_buffers
+    slots, each with a pinned host chunk, a device chunk, SoA hit buffers
+    and a selection bound to them (the batched plan, or the plain form), and
+    its own stream.  submit() fills the next slot's pinned chunk through
+    `fill(view)` (the readout writing into host memory), then queues on the
+    slot's stream: the copy to the GPU, mu3e_chunk_unpack, the selection and
+    the copy of the frame flags back; so one chunk's copies overlap another
+    chunk's selection.  A slot is reused once its previous chunk is done."""
+
+    def __init__(self, params: dict, chunk_bytes: int, max_frames: int, n_buffers: int = 3, form: str = "batched",
+                 triplet_capacity: int | None = None, track_capacity: int | None = None, tuning: dict | None = None,
+                 device="cuda"):
+        import torch
+        L = load()
+        self.chunk_bytes = int(chunk_bytes) // 16 * 16
+        self.max_frames = int(max_frames)
+        self.max_hits = chunk_capacity(self.chunk_bytes, self.max_frames)
+        if self.max_hits <= 0:
+            raise ValueError("chunk too small for its frame table")
+        self.params = params
+        self.slots = []
+        for _ in range(int(n_buffers)):
+            host = torch.empty(self.chunk_bytes, dtype=torch.uint8, pin_memory=True)
+            dchunk = torch.empty(self.chunk_bytes, dtype=torch.uint8, device=device)
+            x = torch.zeros(self.max_hits, dtype=torch.float32, device=device)
+            y = torch.zeros_like(x)
+            z = torch.zeros_like(x)
+            lo = torch.zeros(4 * self.max_frames + 1, dtype=torch.int32, device=device)
+            info = torch.zeros(2, dtype=torch.int32, device=device)
+            hits = DeviceHits(x, y, z, None, None, lo, self.max_frames, self.max_hits)
+            if form == "batched":
+                sel = BatchedSelector(hits, params, triplet_capacity, track_capacity, device=device, **(tuning or {}))
+            elif form == "plain":
+                sel = Selector(self.max_frames, params, triplet_capacity, track_capacity, device=device)
+            else:
+                raise ValueError(f"form {form!r}: 'batched' or 'plain'")
+            out_flags = torch.empty(self.max_frames, dtype=torch.int32, pin_memory=True)
+            out_info = torch.empty(2, dtype=torch.int32, pin_memory=True)
+            self.slots.append(dict(host=host, dchunk=dchunk, hits=hits, info=info, sel=sel, stream=torch.cuda.Stream(device),
+                                   event=None, out_flags=out_flags, out_info=out_info))
+        self.next = 0
+        self.L = L
+
+    def submit(self, fill) -> int:
+        """fill(host_view: np.ndarray uint8) writes a chunk into the next
+        slot's pinned buffer; returns the slot index (for result())."""
+        import torch
+        k = self.next
+        self.next = (k + 1) % len(self.slots)
+        sl = self.slots[k]
+        if sl["event"] is not None:
+            sl["event"].synchronize()   # the slot's previous chunk is done
+        fill(sl["host"].numpy())
+        st = sl["stream"]
+        with torch.cuda.stream(st):
+            sl["dchunk"].copy_(sl["host"], non_blocking=True)
+            h = sl["hits"]
+            _check(self.L.mu3e_chunk_unpack(_ptr(sl["dchunk"]), self.chunk_bytes, self.max_frames, self.max_hits,
+                                            _ptr(h.x), _ptr(h.y), _ptr(h.z), _ptr(h.layer_offsets), _ptr(sl["info"]),
+                                            _stream(st)), "mu3e_chunk_unpack")
+            if isinstance(sl["sel"], BatchedSelector):
+                sl["sel"].run(None, st)
+            else:
+                sl["sel"].run(h, st)
+            sl["out_flags"].copy_(sl["sel"].flags[:self.max_frames], non_blocking=True)
+            sl["out_info"].copy_(sl["info"], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        sl["event"] = ev
+        return k
+
+    def result(self, k: int):
+        """(frames, flags[frames]) of the chunk last submitted to slot k
+        (waits for it); frames = -1 for a malformed chunk."""
+        sl = self.slots[k]
+        sl["event"].synchronize()
+        F = int(sl["out_info"][0])
+        return F, sl["out_flags"].numpy()[:max(F, 0)].view(np.uint32).copy()
+
+    def synchronize(self):
+        for sl in self.slots:
+            if sl["event"] is not None:
+                sl["event"].synchronize()
 
 
 def select_frames(hits: DeviceHits, params: dict, stream=None, **kw):

@@ -168,3 +168,32 @@ def test_fit_autograd_rejects_wrong_coordinates(L):
         lib.fit_chi2_autograd(x, hits.y, hits.z, hits, trip, default_params())
     with pytest.raises(ValueError, match="x"):
         lib.fit_chi2_autograd(hits.x, hits.y, hits.z, hits, trip, default_params())   # host tensors
+
+
+def test_chunk_layout_and_validation(L):
+    """The chunk a readout writes (records from the front, the layer offsets
+    and the frame count at the tail) as the binding packs it, and the host
+    checks of mu3e_chunk_unpack (nothing is launched)."""
+    import numpy as np
+    from paper_2206_11535_amd import lib, synth
+    fs = synth.generate(2, n_frames=40)
+    buf = np.full(1 << 16, 0xAB, np.uint8)
+    n = lib.pack_chunk(fs, 5, 25, buf)
+    lo = fs.layer_offsets
+    assert n == lo[100] - lo[20]
+    rec = buf[:12 * n].view(np.float32).reshape(-1, 3)
+    assert np.array_equal(rec[:, 0], fs.x[lo[20]:lo[100]]) and np.array_equal(rec[:, 2], fs.z[lo[20]:lo[100]])
+    tail = buf[len(buf) - 4 * 82:].view(np.int32)
+    assert tail[-1] == 20 and tail[0] == 0 and tail[-2] == n
+    assert np.array_equal(tail[:-1], lo[20:101] - lo[20])
+    assert lib.chunk_capacity(1 << 16, 20) == ((1 << 16) - 4 - 4 * 81) // 12
+    with pytest.raises(ValueError):
+        lib.pack_chunk(fs, 0, 40, np.zeros(4096, np.uint8))
+    P = ctypes.c_void_p
+    # null chunk, too short, misaligned, negative sizes, null outputs
+    assert L.mu3e_chunk_unpack(None, 1024, 10, 100, 16, 32, 48, 64, 80, None) == -1
+    assert L.mu3e_chunk_unpack(P(4096), 2, 10, 100, 16, 32, 48, 64, 80, None) == -1
+    assert L.mu3e_chunk_unpack(P(4098), 1024, 10, 100, 16, 32, 48, 64, 80, None) == -1
+    assert L.mu3e_chunk_unpack(P(4096), 1024, -1, 100, 16, 32, 48, 64, 80, None) == -1
+    assert L.mu3e_chunk_unpack(P(4096), 1024, 10, 100, None, 32, 48, 64, 80, None) == -1
+    assert L.mu3e_chunk_unpack(P(4096), 1024, 10, 100, 16, 32, 48, None, 80, None) == -1

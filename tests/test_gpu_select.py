@@ -679,6 +679,110 @@ def test_energy_passing_triples_equal_oracle(lib):
     assert np.all(ch[rows[:, 1]] > 0) and np.all(ch[rows[:, 2]] > 0) and np.all(ch[rows[:, 3]] < 0)
 
 
+def test_chunks_unpacked_equal_batch(lib):
+    """Frames packed into chunks (records and tail offsets, as the readout
+    writes them), copied to the GPU and unpacked give the same selection as
+    the frames given as SoA arrays; the frames that pad a chunk to its frame
+    table stay empty.  Through ChunkStream with three slots in flight, in
+    both forms, over more chunks than slots."""
+    import torch
+    fs = synth.generate(2, n_frames=7000, salt=41)
+    p = default_params()
+    dh = lib.to_device(fs)
+    ref = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    rf, rc, rv = ref.result()
+    bounds = [0, 1000, 2500, 2501, 4000, 5200, 6500, 7000, 7000]   # uneven chunks, one of one frame, one empty
+    for form in ("batched", "plain"):
+        print(f"case: chunk stream, {form}", flush=True)
+        cs = lib.ChunkStream(p, 1 << 21, 1500, n_buffers=3, form=form)
+        slots = []
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            slots.append((a, b, cs.submit(lambda v, a=a, b=b: lib.pack_chunk(fs, a, b, v))))
+            if len(slots) >= 3:   # results of the oldest chunk before its slot is refilled
+                a0, b0, k0 = slots.pop(0)
+                F, fl = cs.result(k0)
+                assert F == b0 - a0 and np.array_equal(fl, rf[a0:b0])
+        for a0, b0, k0 in slots:
+            F, fl = cs.result(k0)
+            assert F == b0 - a0 and np.array_equal(fl, rf[a0:b0])
+        # the last chunk's full outputs, padding frames included
+        sl = cs.slots[k0]
+        fb, cb, vb = sl["sel"].result()
+        assert not fb[b0 - a0:].any() and not cb[b0 - a0:].any()
+        cs.synchronize()
+    # one chunk through the plain form with the debug lists: same triplets
+    print("case: one chunk, lists", flush=True)
+    cs = lib.ChunkStream(p, 1 << 22, 3000, n_buffers=1, form="plain")
+    k = cs.submit(lambda v: lib.pack_chunk(fs, 2000, 5000, v))
+    F, fl = cs.result(k)
+    sel = cs.slots[k]["sel"]
+    lo_chunk = cs.slots[k]["hits"].layer_offsets.cpu().numpy()
+    t, tr, kf, c = sel.lists(lo_chunk)
+    assert c[2] == 0
+    tr_ref, _, _, _ = ref.lists(fs.layer_offsets)
+    base = fs.layer_offsets[4 * 2000]
+    m = (tr_ref[:, 0] >= 2000) & (tr_ref[:, 0] < 5000)
+    want = tr_ref[m].copy()
+    want[:, 0] -= 2000
+    want[:, 1:] -= base
+    assert sorted(map(tuple, t.tolist())) == sorted(map(tuple, want.tolist()))
+
+
+def test_malformed_chunks(lib):
+    """Chunks whose tail is inconsistent (frame count above the table,
+    offsets overlapping the records, a first offset other than 0, more hits
+    than the buffers hold) are unpacked to no frames with info -1; offsets
+    that decrease inside a consistent tail reach the selection, which skips
+    those frames and reports them."""
+    import torch
+    fs = synth.generate(2, n_frames=300, salt=42)
+    p = default_params()
+    cs = lib.ChunkStream(p, 1 << 20, 400, n_buffers=1, form="plain")
+
+    def bad_count(v):
+        lib.pack_chunk(fs, 0, 300, v)
+        v[len(v) // 4 * 4 - 4:len(v) // 4 * 4].view(np.int32)[0] = 401
+
+    def overlapping(v):
+        v[:] = 0
+        v[len(v) // 4 * 4 - 4:len(v) // 4 * 4].view(np.int32)[0] = (len(v) // 4) // 4
+
+    def first_not_zero(v):
+        lib.pack_chunk(fs, 0, 300, v)
+        t = v[len(v) // 4 * 4 - 4 * (4 * 300 + 2):len(v) // 4 * 4].view(np.int32)
+        t[0] = 1
+
+    def too_many_hits(v):
+        lib.pack_chunk(fs, 0, 300, v)
+        t = v[len(v) // 4 * 4 - 4 * (4 * 300 + 2):len(v) // 4 * 4].view(np.int32)
+        t[-2] = cs.max_hits + 1
+
+    for what, fill in (("count", bad_count), ("overlap", overlapping), ("first", first_not_zero),
+                       ("hits", too_many_hits)):
+        print(f"case: malformed chunk ({what})", flush=True)
+        k = cs.submit(fill)
+        F, fl = cs.result(k)
+        assert F == -1 and len(fl) == 0, what
+        fb, cb, _ = cs.slots[k]["sel"].result()
+        assert not fb.any() and not cb.any(), what
+
+    def decreasing(v):
+        lib.pack_chunk(fs, 0, 300, v)
+        t = v[len(v) // 4 * 4 - 4 * (4 * 300 + 2):len(v) // 4 * 4].view(np.int32)
+        t[4 * 10 + 2] = t[4 * 10 + 1] - 1   # frame 10, layer 1 count negative
+    print("case: chunk with decreasing offsets", flush=True)
+    k = cs.submit(decreasing)
+    F, fl = cs.result(k)
+    assert F == 300
+    assert cs.slots[k]["sel"].counters()[2] & 4
+    dh = lib.to_device(fs)
+    ref = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    rf = ref.result()[0]
+    assert fl[10] == 0 and fl[9] == rf[9] and np.array_equal(fl[12:], rf[12:])
+
+
 def test_vertex_entry_point_malformed(lib):
     """mu3e_vertex on hand-made track ranges: a track with a hit index
     outside [0, n_hits) is ignored (the frame gives what it gives without
