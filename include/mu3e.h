@@ -152,7 +152,9 @@ typedef struct {
   int32_t max_chunks, chunk_size;
 } mu3e_debug_t;
 
-const char *mu3e_status_string(mu3e_status s);
+/* Text of a status code; any int is accepted ("unknown status" outside the
+ * enumeration). */
+const char *mu3e_status_string(int status);
 
 /* Workspace bytes for mu3e_select_frames over n_frames frames with room for
  * triplet_capacity (<= 2^30) selected triplets and track_capacity tracks of

@@ -2103,7 +2103,7 @@ bool hits_ok(const mu3e_hits_t* h) {
 
 extern "C" {
 
-const char* mu3e_status_string(mu3e_status s) {
+const char* mu3e_status_string(int s) {
   switch (s) {
     case MU3E_OK: return "ok";
     case MU3E_ERR_INVALID_ARG: return "invalid argument";

@@ -95,7 +95,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2206_11535_amd.build.build()")
     import torch  # noqa: F401  -- load torch's HIP runtime first
-    L = ctypes.CDLL(path)
+    _lib = declare(ctypes.CDLL(path))
+    return _lib
+
+
+def declare(L):
+    """Declares the argument and result types of the C ABI on a loaded
+    library handle (no GPU call)."""
     P, I, Z = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     L.mu3e_status_string.restype = ctypes.c_char_p
     L.mu3e_status_string.argtypes = [ctypes.c_int]
@@ -144,7 +150,6 @@ def load(path: str = LIB_PATH):
     L.mu3e_align_workspace_size.argtypes = [I]
     L.mu3e_align_backward.restype = ctypes.c_int
     L.mu3e_align_backward.argtypes = [ctypes.POINTER(Hits), P, I, P, I, ctypes.POINTER(Params), P, P, P, Z, P]
-    _lib = L
     return L
 
 
