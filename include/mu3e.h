@@ -304,6 +304,20 @@ mu3e_status mu3e_chunk_unpack(const void *chunk, int64_t chunk_bytes, int32_t ma
                               int32_t max_hits, float *x, float *y, float *z,
                               int32_t *layer_offsets, int32_t *info, hipStream_t stream);
 
+/* ---- Frame pairs (tracks across a frame boundary, Section VII) -----------
+ * Builds the overlapping frame pairs of a batch: merged frame g (0 <= g <
+ * n_frames - 1) holds, per layer, the hits of frame g followed by those of
+ * frame g + 1.  Outputs (device, caller-owned): x, y, z [capacity] with
+ * capacity >= 2 * n_hits (else MU3E_ERR_CAPACITY), layer_offsets
+ * [4 * (n_frames - 1) + 1] with layer_offsets[4g + l] = lo[4g + l] +
+ * lo[4g + 4 + l] - lo[4].  Running the selection on the merged frames
+ * (n_frames - 1 frames, layer_offsets[4 (n_frames - 1)] hits) finds the
+ * tracks whose hits fall into two consecutive frames: a hit with local
+ * index k on layer l of merged frame g comes from frame g when k is below
+ * frame g's count on that layer, else from frame g + 1.  Needs n_frames >= 2. */
+mu3e_status mu3e_pair_frames(const mu3e_hits_t *hits, float *x, float *y, float *z,
+                             int32_t *layer_offsets, int64_t capacity, hipStream_t stream);
+
 /* ---- Batched form ------------------------------------------------------
  * A plan captures the whole selection of one batch of frames into a HIP
  * graph around one persistent kernel: waves take the frames of the batch

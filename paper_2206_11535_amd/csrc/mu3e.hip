@@ -1771,6 +1771,41 @@ k_unpack(const unsigned char* __restrict__ chunk, long long bytes, int max_frame
   }
 }
 
+// =========================================================== frame pairs
+// Overlapping frame pairs (tracks across a frame boundary, Section VII):
+// merged frame g holds, per layer, the hits of frame g and then those of
+// frame g + 1, so that the selection run on the merged frames finds tracks
+// whose hits fall into two consecutive frames.  Its layer offsets have a
+// closed form, lo'[4g + l] = lo[4g + l] + lo[4g + 4 + l] - lo[4]; one wave
+// per (frame, layer) segment of the input copies its hits to their two
+// places (the first part of merged frame f, the second of merged frame
+// f - 1).  Writes stay inside [0, cap) whatever the offsets; malformed
+// input offsets give malformed merged offsets, which the selection skips.
+__global__ void __launch_bounds__(256)
+k_pairs(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+        const int32_t* __restrict__ lo, int F, int n_hits, float* __restrict__ Xo, float* __restrict__ Yo,
+        float* __restrict__ Zo, int32_t* __restrict__ loo, long long cap) {
+  const int lane = (int)threadIdx.x % kWave;
+  const int waves = (int)(gridDim.x * blockDim.x) / kWave;
+  const int base4 = F > 1 ? lo[4] : 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= 4 * (F - 1); t += gridDim.x * blockDim.x)
+    loo[t] = lo[t] + lo[t + 4] - base4;
+  for (int seg = (int)(blockIdx.x * blockDim.x + threadIdx.x) / kWave; seg < 4 * F; seg += waves) {
+    const int f = seg >> 2, l = seg & 3;
+    const int a = lo[seg], b = lo[seg + 1];
+    if (a < 0 || b < a || b > n_hits) continue;
+    // first part of merged frame f, second part of merged frame f - 1
+    const long long d0 = f < F - 1 ? (long long)lo[seg] + lo[seg + 4] - base4 : -1;
+    const long long d1 = f > 0 ? (long long)lo[seg - 4] + lo[seg] - base4 + (lo[seg - 3] - lo[seg - 4]) : -1;
+    for (int i = a + lane; i < b; i += kWave) {
+      const float x = X[i], y = Y[i], z = Z[i];
+      const long long o0 = d0 + (i - a), o1 = d1 + (i - a);
+      if (d0 >= 0 && o0 < cap) { Xo[o0] = x; Yo[o0] = y; Zo[o0] = z; }
+      if (d1 >= 0 && o1 >= 0 && o1 < cap) { Xo[o1] = x; Yo[o1] = y; Zo[o1] = z; }
+    }
+  }
+}
+
 // ================================================================== k_fit
 __global__ void __launch_bounds__(256)
 k_fit(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
@@ -1839,9 +1874,11 @@ __global__ void __launch_bounds__(256)
 k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
             const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
             const float* __restrict__ theta, int n_sensors, Consts C, const float* __restrict__ gchi2,
-            double* __restrict__ partial) {
+            double* __restrict__ partial, int32_t* __restrict__ done, int ndone) {
   extern __shared__ double acc[];   // 4 * n_sensors float64 accumulators
   const int np = 4 * n_sensors;
+  if (blockIdx.x == 0)   // the reduction's counters start at zero (the workspace arrives uncleared)
+    for (int j = threadIdx.x; j < ndone; j += blockDim.x) done[j] = 0;
   for (int j = threadIdx.x; j < np; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
@@ -1860,30 +1897,52 @@ k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const floa
   for (int j = threadIdx.x; j < np; j += blockDim.x) partial[(size_t)blockIdx.x * np + j] = acc[j];
 }
 
-// Column sums of the per-block rows of partial ([blocks][np] float64):
-// block x takes 64 columns, each of its four waves every fourth row with
-// eight independent sums per lane (so that eight loads are in flight), the
-// eight and then the four waves' sums added in a fixed order (the result is
-// deterministic).
+// Column sums of the per-block rows of partial ([blocks][np] float64), in
+// two levels within one launch: block (x, g) takes 64 columns and the rows
+// of group g (blocks / kAlignGroups of them), each of its four waves every
+// fourth row with eight independent sums per lane (so that eight loads are
+// in flight), and writes its group sum to part2[g]; the last block of
+// column block x to finish (a counter per column block, reset by it for the
+// next call) adds the kAlignGroups group sums in order.  Every sum is taken
+// in a fixed order, so the result is deterministic.
+constexpr int kAlignGroups = 16;
+
 __global__ void __launch_bounds__(256)
-k_align_reduce(const double* __restrict__ partial, int blocks, int np, float* __restrict__ grad) {
+k_align_reduce(const double* __restrict__ partial, int blocks, int np, double* __restrict__ part2,
+               int32_t* __restrict__ done, float* __restrict__ grad) {
   __shared__ double part[4][kWave];
+  __shared__ int last;
   const int l = (int)threadIdx.x % kWave, w = (int)threadIdx.x / kWave;
   const int j = (int)blockIdx.x * kWave + l;
+  const int rows = (blocks + kAlignGroups - 1) / kAlignGroups;
+  const int r0 = (int)blockIdx.y * rows, r1 = min(blocks, r0 + rows);
   double s = 0.0;
   if (j < np) {
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int b = w;
-    for (; b + 28 < blocks; b += 32) {   // rows b, b + 4, ..., b + 28
+    int b = r0 + w;
+    for (; b + 28 < r1; b += 32) {   // rows b, b + 4, ..., b + 28
 #pragma unroll
       for (int k = 0; k < 8; ++k) a[k] += partial[(size_t)(b + 4 * k) * np + j];
     }
-    for (; b < blocks; b += 4) a[0] += partial[(size_t)b * np + j];
+    for (; b < r1; b += 4) a[0] += partial[(size_t)b * np + j];
     s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   part[w][l] = s;
   __syncthreads();
-  if (w == 0 && j < np) grad[j] = (float)((part[0][l] + part[1][l]) + (part[2][l] + part[3][l]));
+  if (w == 0 && j < np) part2[(size_t)blockIdx.y * np + j] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&done[blockIdx.x], 1) == kAlignGroups - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (w == 0 && j < np) {
+    double t = 0.0;
+    for (int g = 0; g < kAlignGroups; ++g) t += __hip_atomic_load(&part2[(size_t)g * np + j], __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT);
+    grad[j] = (float)t;
+  }
+  if (threadIdx.x == 0) done[blockIdx.x] = 0;
 }
 
 // Start of a run: counters cleared except counters[7] = handed0 (the
@@ -2238,6 +2297,19 @@ mu3e_status mu3e_chunk_unpack(const void* chunk, int64_t chunk_bytes, int32_t ma
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
+mu3e_status mu3e_pair_frames(const mu3e_hits_t* hits, float* x, float* y, float* z, int32_t* layer_offsets,
+                             int64_t capacity, hipStream_t stream) {
+  if (!hits_ok(hits) || hits->n_frames < 2 || !layer_offsets || capacity < 0) return MU3E_ERR_INVALID_ARG;
+  if (capacity < 2 * (int64_t)hits->n_hits) return MU3E_ERR_CAPACITY;
+  if (capacity > 0 && (!x || !y || !z)) return MU3E_ERR_INVALID_ARG;
+  const int cus = device_cus();
+  const int64_t segs = 4 * (int64_t)hits->n_frames;
+  const int blocks = (int)((segs + 3) / 4 < cus * 16 ? (segs + 3) / 4 : cus * 16);
+  hipLaunchKernelGGL(k_pairs, dim3(blocks), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets,
+                     hits->n_frames, hits->n_hits, x, y, z, layer_offsets, (long long)capacity);
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
 mu3e_status mu3e_fit_triplets(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const mu3e_params_t* params,
                               float* out, hipStream_t stream) {
   if (!hits || hits->n_hits < 0 || n < 0 || !params || (n > 0 && (!trip || !out || !hits->x || !hits->y || !hits->z)))
@@ -2309,9 +2381,25 @@ mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t* hits, const int32_t* t
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
+// Workspace of mu3e_align_backward: the per-block rows, the group sums and
+// the reduction's counters (one per 64 columns).
+struct AlignLayout {
+  size_t partial, part2, done, total;
+};
+
+static AlignLayout align_layout(int n_sensors) {
+  const size_t np = 4 * (size_t)n_sensors;
+  AlignLayout L;
+  L.partial = 0;
+  L.part2 = align256((size_t)kAlignBlocks * np * sizeof(double));
+  L.done = L.part2 + align256((size_t)kAlignGroups * np * sizeof(double));
+  L.total = L.done + align256((np + kWave - 1) / kWave * sizeof(int32_t));
+  return L;
+}
+
 size_t mu3e_align_workspace_size(int32_t n_sensors) {
   if (n_sensors <= 0 || n_sensors > kAlignMaxSensors) return 0;
-  return align256((size_t)kAlignBlocks * 4 * n_sensors * sizeof(double));
+  return align_layout(n_sensors).total;
 }
 
 static bool align_args_ok(const mu3e_hits_t* hits, const int32_t* trip, int32_t n, const float* theta,
@@ -2343,13 +2431,18 @@ mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, in
   if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
   if (n_sensors > kAlignMaxSensors) return MU3E_ERR_UNSUPPORTED;
   if (!workspace || workspace_bytes < mu3e_align_workspace_size(n_sensors)) return MU3E_ERR_CAPACITY;
-  double* partial = static_cast<double*>(workspace);
+  const AlignLayout AL = align_layout(n_sensors);
+  char* ws = static_cast<char*>(workspace);
+  double* partial = reinterpret_cast<double*>(ws + AL.partial);
+  double* part2 = reinterpret_cast<double*>(ws + AL.part2);
+  int32_t* done = reinterpret_cast<int32_t*>(ws + AL.done);
   const int np = 4 * n_sensors;
+  const int ncb = (np + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_align_bwd, dim3(kAlignBlocks), dim3(256), (size_t)np * sizeof(double), stream, hits->x, hits->y,
-                     hits->z, hits->sensor,
-                     hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial);
-  hipLaunchKernelGGL(k_align_reduce, dim3((np + kWave - 1) / kWave), dim3(256), 0, stream, partial, kAlignBlocks, np,
-                     grad_theta);
+                     hits->z, hits->sensor, hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial, done,
+                     ncb);
+  hipLaunchKernelGGL(k_align_reduce, dim3(ncb, kAlignGroups), dim3(256), 0, stream, partial, kAlignBlocks, np, part2,
+                     done, grad_theta);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 

@@ -118,6 +118,8 @@ def declare(L):
                                             ctypes.POINTER(Debug), P]
     L.mu3e_chunk_unpack.restype = ctypes.c_int
     L.mu3e_chunk_unpack.argtypes = [P, ctypes.c_int64, I, I, P, P, P, P, P, P]
+    L.mu3e_pair_frames.restype = ctypes.c_int
+    L.mu3e_pair_frames.argtypes = [ctypes.POINTER(Hits), P, P, P, P, ctypes.c_int64, P]
     L.mu3e_fit_triplets.restype = ctypes.c_int
     L.mu3e_fit_triplets.argtypes = [ctypes.POINTER(Hits), P, I, ctypes.POINTER(Params), P, P]
     L.mu3e_fit_triplets_backward.restype = ctypes.c_int
@@ -380,6 +382,26 @@ class BatchedSelector(Selector):
         if plan is not None and _lib is not None:
             _lib.mu3e_plan_destroy(plan)
             self.plan = None
+
+
+def pair_frames(hits: DeviceHits, stream=None) -> DeviceHits:
+    """The overlapping frame pairs of a batch (mu3e_pair_frames): merged
+    frame g holds, per layer, frame g's hits and then frame g + 1's.  The
+    returned hits are sized for 2 * n_hits; their n_hits is that capacity
+    (the offsets hold the real count)."""
+    import torch
+    if hits.n_frames < 2:
+        raise ValueError("frame pairs need at least two frames")
+    cap = 2 * hits.n_hits
+    dev = hits.x.device
+    x = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    lo = torch.empty(4 * (hits.n_frames - 1) + 1, dtype=torch.int32, device=dev)
+    hs = hits.struct()
+    _check(load().mu3e_pair_frames(ctypes.byref(hs), _ptr(x), _ptr(y), _ptr(z), _ptr(lo), cap, _stream(stream)),
+           "mu3e_pair_frames")
+    return DeviceHits(x, y, z, None, None, lo, hits.n_frames - 1, cap)
 
 
 # ------------------------------------------------------------ chunk ingest

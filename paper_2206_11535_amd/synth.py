@@ -29,7 +29,9 @@ Draw order (fixed, one PCG64 stream per configuration):
   3 signal flags, 4 decay vertices, 5 Michel momenta, 6 Michel directions,
   7 signal kinematics (Dalitz point, orientation), 8 scattering angles
   (per layer, two per particle), 9 noise hits, 10 in-layer shuffle keys,
-  11 misalignment.
+  11 misalignment, 12 frame-straddling particles and their first layer in
+  the next frame (only when straddle_frac > 0, so that other configurations
+  draw nothing).
 """
 from __future__ import annotations
 
@@ -70,6 +72,7 @@ class SynthConfig:
     misalign: bool = False
     misalign_t: float = 0.05      # mm
     misalign_alpha: float = 0.5e-3  # rad
+    straddle_frac: float = 0.0    # particles whose later hits fall into the next frame
 
 
 CONFIGS = {
@@ -82,6 +85,10 @@ CONFIGS = {
                    misalign=True),
     # phase II of the experiment: 1e9 mu/s, ten times the nominal rate
     6: SynthConfig("phase-II lambda=64", 100_000, 64.0, 5, 0.01, 6),
+    # nominal rate with 5 % of the particles crossing a frame boundary
+    # between two layers (their hits from that layer on belong to the next
+    # 64 ns frame)
+    7: SynthConfig("nominal lambda=6.4, frame-straddling", 100_000, 6.4, 5, 0.01, 7, straddle_frac=0.05),
 }
 
 
@@ -395,6 +402,17 @@ def generate(cfg: SynthConfig | int, n_frames: Optional[int] = None,
         charge[is_sig] = np.tile([1.0, -1.0, 1.0], n_sigf)
     # 8 propagation with scattering
     pid, lay, hx, hy, hz = propagate(rng, pos, mom, charge)
+    hit_frame = frame_of[pid]
+    # 12 frame-straddling particles (own stream, so the main draw order is
+    # unchanged): a particle crossing the boundary between layers s - 1 and
+    # s leaves its hits on layers >= s in the next frame
+    straddle = np.full(P, -1, np.int64)
+    if cfg.straddle_frac > 0:
+        rs = _rng(cfg.cfg_id, 2000 + salt)
+        cross = rs.uniform(0.0, 1.0, P) < cfg.straddle_frac
+        first = rs.integers(1, 4, P)
+        straddle = np.where(cross & (frame_of < F - 1), first, -1)
+        hit_frame = hit_frame + ((straddle[pid] >= 0) & (lay >= straddle[pid]))
     # 9 noise
     nn = cfg.noise_per_layer
     nlay = np.tile(np.repeat(np.arange(4), nn), F)
@@ -406,7 +424,7 @@ def generate(cfg: SynthConfig | int, n_frames: Optional[int] = None,
     # a pixel centre just outside the acceptance moves one pixel inward
     nz_ = np.where(np.abs(nz_) > Z_HALF[nlay], nz_ - np.sign(nz_) * PIXEL, nz_)
     # assemble and sort by (frame, layer, shuffle key)
-    all_frame = np.concatenate([frame_of[pid], nframe])
+    all_frame = np.concatenate([hit_frame, nframe])
     all_layer = np.concatenate([lay, nlay]).astype(np.int64)
     all_x = np.concatenate([hx, nx_])
     all_y = np.concatenate([hy, ny_])
@@ -432,7 +450,7 @@ def generate(cfg: SynthConfig | int, n_frames: Optional[int] = None,
     seg = all_frame * 4 + all_layer
     lo = np.searchsorted(seg, np.arange(4 * F + 1)).astype(np.int32)
     parts = dict(frame=frame_of, charge=charge.astype(np.int8), p0=mom,
-                 vertex=pos, signal=is_sig, lam=lam)
+                 vertex=pos, signal=is_sig, lam=lam, straddle=straddle)
     return FrameSet(all_x.astype(np.float32), all_y.astype(np.float32),
                     all_z.astype(np.float32), all_layer.astype(np.uint16),
                     sensor.astype(np.uint16), lo, all_pid.astype(np.int32),

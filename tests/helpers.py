@@ -107,3 +107,23 @@ def circle_intersections(ca, ra, cb, rb, n=20001):
         r = optimize.brentq(g, t[i], t[i + 1], xtol=1e-15, rtol=1e-15)
         out.append(ca + ra * np.array([np.cos(r), np.sin(r)]))
     return out
+
+
+def merge_pairs(fs):
+    """Host construction of the overlapping frame pairs (the plain
+    definition the GPU's k_pairs must reproduce): merged frame g holds, per
+    layer, the hits of frame g and then those of frame g + 1.  Returns
+    (x, y, z, layer_offsets, orig) with orig[i] the input index of merged
+    hit i."""
+    lo = np.asarray(fs.layer_offsets, np.int64)
+    F = (len(lo) - 1) // 4
+    idx, off = [], [0]
+    for g in range(F - 1):
+        for l in range(4):
+            a = np.arange(lo[4 * g + l], lo[4 * g + l + 1])
+            b = np.arange(lo[4 * g + 4 + l], lo[4 * g + 5 + l])
+            idx.append(a)
+            idx.append(b)
+            off.append(off[-1] + len(a) + len(b))
+    orig = np.concatenate(idx) if idx else np.zeros(0, np.int64)
+    return (fs.x[orig], fs.y[orig], fs.z[orig], np.asarray(off, np.int32), orig)

@@ -783,6 +783,54 @@ def test_malformed_chunks(lib):
     assert fl[10] == 0 and fl[9] == rf[9] and np.array_equal(fl[12:], rf[12:])
 
 
+def test_frame_pairs_find_tracks_across_frames(lib):
+    """Tracks across a frame boundary (Section VII): the merged frame pairs
+    built on the GPU equal their host definition bit for bit; the selection
+    on them matches the oracle run on the host-built pairs; and of the
+    generator's particles that cross a frame boundary with a hit on every
+    layer, the frame pairs find most as tracks with exactly their four hits,
+    which the frames on their own cannot (their hits sit in two frames)."""
+    import torch
+    from helpers import Frames, merge_pairs
+    fs = synth.generate(7, n_frames=2000, salt=51)
+    p = default_params()
+    dh = lib.to_device(fs)
+    print("case: frame pairs of 2000 frames", flush=True)
+    ph = lib.pair_frames(dh)
+    torch.cuda.synchronize()
+    x, y, z, off, orig = merge_pairs(fs)
+    n = int(off[-1])
+    assert np.array_equal(ph.layer_offsets.cpu().numpy(), off)
+    assert np.array_equal(ph.x[:n].cpu().numpy(), x) and np.array_equal(ph.y[:n].cpu().numpy(), y)
+    assert np.array_equal(ph.z[:n].cpu().numpy(), z)
+    pf = synth.FrameSet(x, y, z, np.zeros(n, np.uint16), np.zeros(n, np.uint16), off, fs.pid[orig], {},
+                        np.zeros(fs.n_frames - 1, bool))
+    sel = lib.select_frames(ph, p)
+    torch.cuda.synchronize()
+    flags, counts, vtx = sel.result()
+    trips, tracks, kf, c = sel.lists(off)
+    assert c[2] == 0
+    orc = oracle.run(pf, p)
+    bad, stats = compare(orc, flags, counts, vtx, trips, tracks, kf)
+    print("frame pairs", stats, flush=True)
+    assert_parity(bad, stats, "frame pairs")
+    # recovery of the particles that cross a frame boundary
+    _, _, table = synth.true_triplets(fs)
+    st = fs.particles["straddle"][:len(table)]
+    cross = (st >= 0) & np.all(table >= 0, axis=1)
+    assert cross.sum() > 100
+    want = {tuple(r) for r in table[cross].tolist()}
+    found_pairs = {tuple(r) for r in orig[tracks[:, 1:5]].tolist()} & want
+    single = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    _, tr1, _, _ = single.lists(fs.layer_offsets)
+    found_single = {tuple(r) for r in tr1[:, 1:5].tolist()} & want
+    eff_pairs, eff_single = len(found_pairs) / len(want), len(found_single) / len(want)
+    print(f"crossing particles {len(want)}: found by the pairs {eff_pairs:.3f}, by the frames {eff_single:.3f}",
+          flush=True)
+    assert eff_single == 0.0 and eff_pairs > 0.7
+
+
 def test_vertex_entry_point_malformed(lib):
     """mu3e_vertex on hand-made track ranges: a track with a hit index
     outside [0, n_hits) is ignored (the frame gives what it gives without
