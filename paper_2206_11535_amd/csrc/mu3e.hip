@@ -1777,10 +1777,11 @@ k_unpack(const unsigned char* __restrict__ chunk, long long bytes, int max_frame
 // frame g + 1, so that the selection run on the merged frames finds tracks
 // whose hits fall into two consecutive frames.  Its layer offsets have a
 // closed form, lo'[4g + l] = lo[4g + l] + lo[4g + 4 + l] - lo[4]; one wave
-// per (frame, layer) segment of the input copies its hits to their two
-// places (the first part of merged frame f, the second of merged frame
-// f - 1).  Writes stay inside [0, cap) whatever the offsets; malformed
-// input offsets give malformed merged offsets, which the selection skips.
+// per input frame copies its hits to their two places (the first part of
+// merged frame f, the second of merged frame f - 1).  Writes stay inside
+// [0, cap) whatever the offsets (a frame whose own offsets are malformed is
+// not copied); malformed input offsets give malformed merged offsets, which
+// the selection skips.
 __global__ void __launch_bounds__(256)
 k_pairs(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
         const int32_t* __restrict__ lo, int F, int n_hits, float* __restrict__ Xo, float* __restrict__ Yo,
@@ -1790,18 +1791,33 @@ k_pairs(const float* __restrict__ X, const float* __restrict__ Y, const float* _
   const int base4 = F > 1 ? lo[4] : 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= 4 * (F - 1); t += gridDim.x * blockDim.x)
     loo[t] = lo[t] + lo[t + 4] - base4;
-  for (int seg = (int)(blockIdx.x * blockDim.x + threadIdx.x) / kWave; seg < 4 * F; seg += waves) {
-    const int f = seg >> 2, l = seg & 3;
-    const int a = lo[seg], b = lo[seg + 1];
-    if (a < 0 || b < a || b > n_hits) continue;
-    // first part of merged frame f, second part of merged frame f - 1
-    const long long d0 = f < F - 1 ? (long long)lo[seg] + lo[seg + 4] - base4 : -1;
-    const long long d1 = f > 0 ? (long long)lo[seg - 4] + lo[seg] - base4 + (lo[seg - 3] - lo[seg - 4]) : -1;
-    for (int i = a + lane; i < b; i += kWave) {
+  // one wave per input frame, lanes over its hits (all four layers)
+  for (int f = (int)(blockIdx.x * blockDim.x + threadIdx.x) / kWave; f < F; f += waves) {
+    const int o = lane < 5 ? lo[4 * f + lane] : 0;
+    const int b0 = lane_value(o, 0), b4 = lane_value(o, 4);
+    int bl[5], good = b0 >= 0 && b4 <= n_hits;
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      bl[l] = lane_value(o, l);
+      if (l > 0) good = good && bl[l] >= bl[l - 1];
+    }
+    if (!good) continue;
+    // where layer l of frame f starts as the first part of merged frame f
+    // and after frame f - 1's hits in merged frame f - 1
+    long long d0[4], d1[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      d0[l] = f < F - 1 ? (long long)bl[l] + lo[4 * f + 4 + l] - base4 : -1;
+      d1[l] = f > 0 ? (long long)lo[4 * f - 4 + l] + bl[l] - base4 + (lo[4 * f - 3 + l] - lo[4 * f - 4 + l]) : -1;
+    }
+    for (int i = b0 + lane; i < b4; i += kWave) {
+      const int l = (i >= bl[1]) + (i >= bl[2]) + (i >= bl[3]);
+      const long long k = i - (l == 0 ? bl[0] : l == 1 ? bl[1] : l == 2 ? bl[2] : bl[3]);
+      const long long e0 = l == 0 ? d0[0] : l == 1 ? d0[1] : l == 2 ? d0[2] : d0[3];
+      const long long e1 = l == 0 ? d1[0] : l == 1 ? d1[1] : l == 2 ? d1[2] : d1[3];
       const float x = X[i], y = Y[i], z = Z[i];
-      const long long o0 = d0 + (i - a), o1 = d1 + (i - a);
-      if (d0 >= 0 && o0 < cap) { Xo[o0] = x; Yo[o0] = y; Zo[o0] = z; }
-      if (d1 >= 0 && o1 >= 0 && o1 < cap) { Xo[o1] = x; Yo[o1] = y; Zo[o1] = z; }
+      if (e0 >= 0 && e0 + k < cap) { Xo[e0 + k] = x; Yo[e0 + k] = y; Zo[e0 + k] = z; }
+      if (e1 >= 0 && e1 + k < cap) { Xo[e1 + k] = x; Yo[e1 + k] = y; Zo[e1 + k] = z; }
     }
   }
 }
@@ -1874,11 +1890,9 @@ __global__ void __launch_bounds__(256)
 k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
             const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
             const float* __restrict__ theta, int n_sensors, Consts C, const float* __restrict__ gchi2,
-            double* __restrict__ partial, int32_t* __restrict__ done, int ndone) {
+            double* __restrict__ partial) {
   extern __shared__ double acc[];   // 4 * n_sensors float64 accumulators
   const int np = 4 * n_sensors;
-  if (blockIdx.x == 0)   // the reduction's counters start at zero (the workspace arrives uncleared)
-    for (int j = threadIdx.x; j < ndone; j += blockDim.x) done[j] = 0;
   for (int j = threadIdx.x; j < np; j += blockDim.x) acc[j] = 0.0;
   __syncthreads();
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
@@ -1898,20 +1912,20 @@ k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const floa
 }
 
 // Column sums of the per-block rows of partial ([blocks][np] float64), in
-// two levels within one launch: block (x, g) takes 64 columns and the rows
+// two kernels: block (x, g) of k_align_reduce takes 64 columns and the rows
 // of group g (blocks / kAlignGroups of them), each of its four waves every
 // fourth row with eight independent sums per lane (so that eight loads are
-// in flight), and writes its group sum to part2[g]; the last block of
-// column block x to finish (a counter per column block, reset by it for the
-// next call) adds the kAlignGroups group sums in order.  Every sum is taken
-// in a fixed order, so the result is deterministic.
+// in flight), and writes its group sum to part2[g]; k_align_reduce2 adds the
+// kAlignGroups group sums of each column in order.  Every sum is taken in a
+// fixed order, so the result is deterministic.  (A single launch in which
+// the last block of each column group adds the group sums needs
+// device-scope fences, which write back the L2 of every XCD: it ran twice as
+// long as both kernels together.)
 constexpr int kAlignGroups = 16;
 
 __global__ void __launch_bounds__(256)
-k_align_reduce(const double* __restrict__ partial, int blocks, int np, double* __restrict__ part2,
-               int32_t* __restrict__ done, float* __restrict__ grad) {
+k_align_reduce(const double* __restrict__ partial, int blocks, int np, double* __restrict__ part2) {
   __shared__ double part[4][kWave];
-  __shared__ int last;
   const int l = (int)threadIdx.x % kWave, w = (int)threadIdx.x / kWave;
   const int j = (int)blockIdx.x * kWave + l;
   const int rows = (blocks + kAlignGroups - 1) / kAlignGroups;
@@ -1930,19 +1944,15 @@ k_align_reduce(const double* __restrict__ partial, int blocks, int np, double* _
   part[w][l] = s;
   __syncthreads();
   if (w == 0 && j < np) part2[(size_t)blockIdx.y * np + j] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&done[blockIdx.x], 1) == kAlignGroups - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (w == 0 && j < np) {
-    double t = 0.0;
-    for (int g = 0; g < kAlignGroups; ++g) t += __hip_atomic_load(&part2[(size_t)g * np + j], __ATOMIC_RELAXED,
-                                                                  __HIP_MEMORY_SCOPE_AGENT);
-    grad[j] = (float)t;
-  }
-  if (threadIdx.x == 0) done[blockIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_align_reduce2(const double* __restrict__ part2, int np, float* __restrict__ grad) {
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= np) return;
+  double t = 0.0;
+  for (int g = 0; g < kAlignGroups; ++g) t += part2[(size_t)g * np + j];
+  grad[j] = (float)t;
 }
 
 // Start of a run: counters cleared except counters[7] = handed0 (the
@@ -2303,8 +2313,8 @@ mu3e_status mu3e_pair_frames(const mu3e_hits_t* hits, float* x, float* y, float*
   if (capacity < 2 * (int64_t)hits->n_hits) return MU3E_ERR_CAPACITY;
   if (capacity > 0 && (!x || !y || !z)) return MU3E_ERR_INVALID_ARG;
   const int cus = device_cus();
-  const int64_t segs = 4 * (int64_t)hits->n_frames;
-  const int blocks = (int)((segs + 3) / 4 < cus * 16 ? (segs + 3) / 4 : cus * 16);
+  const int64_t waves = hits->n_frames;
+  const int blocks = (int)((waves + 3) / 4 < cus * 16 ? (waves + 3) / 4 : cus * 16);
   hipLaunchKernelGGL(k_pairs, dim3(blocks), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->layer_offsets,
                      hits->n_frames, hits->n_hits, x, y, z, layer_offsets, (long long)capacity);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
@@ -2381,10 +2391,9 @@ mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t* hits, const int32_t* t
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
-// Workspace of mu3e_align_backward: the per-block rows, the group sums and
-// the reduction's counters (one per 64 columns).
+// Workspace of mu3e_align_backward: the per-block rows and the group sums.
 struct AlignLayout {
-  size_t partial, part2, done, total;
+  size_t partial, part2, total;
 };
 
 static AlignLayout align_layout(int n_sensors) {
@@ -2392,8 +2401,7 @@ static AlignLayout align_layout(int n_sensors) {
   AlignLayout L;
   L.partial = 0;
   L.part2 = align256((size_t)kAlignBlocks * np * sizeof(double));
-  L.done = L.part2 + align256((size_t)kAlignGroups * np * sizeof(double));
-  L.total = L.done + align256((np + kWave - 1) / kWave * sizeof(int32_t));
+  L.total = L.part2 + align256((size_t)kAlignGroups * np * sizeof(double));
   return L;
 }
 
@@ -2435,14 +2443,12 @@ mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, in
   char* ws = static_cast<char*>(workspace);
   double* partial = reinterpret_cast<double*>(ws + AL.partial);
   double* part2 = reinterpret_cast<double*>(ws + AL.part2);
-  int32_t* done = reinterpret_cast<int32_t*>(ws + AL.done);
   const int np = 4 * n_sensors;
   const int ncb = (np + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_align_bwd, dim3(kAlignBlocks), dim3(256), (size_t)np * sizeof(double), stream, hits->x, hits->y,
-                     hits->z, hits->sensor, hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial, done,
-                     ncb);
-  hipLaunchKernelGGL(k_align_reduce, dim3(ncb, kAlignGroups), dim3(256), 0, stream, partial, kAlignBlocks, np, part2,
-                     done, grad_theta);
+                     hits->z, hits->sensor, hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial);
+  hipLaunchKernelGGL(k_align_reduce, dim3(ncb, kAlignGroups), dim3(256), 0, stream, partial, kAlignBlocks, np, part2);
+  hipLaunchKernelGGL(k_align_reduce2, dim3((np + 255) / 256), dim3(256), 0, stream, part2, np, grad_theta);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
