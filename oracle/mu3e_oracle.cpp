@@ -446,6 +446,144 @@ VertexOut vertex_triple(const Track* T[3], const Params& P) {
   return r;
 }
 
+// ============================================================ Refined vertex
+// Section VII names a more precise vertex reconstruction than the rough
+// estimate of Section IV-C as the next step; the paper gives no formula.
+// Reading taken here: the refined vertex of an e+ e+ e- triple is the point v
+// that minimises
+//     J(v, phi) = sum_k |H_k(phi_k) - v|^2 / sigma_k^2
+// jointly over v and one turning angle phi_k per track.  H_k(phi) is the point
+// of track k's helix reached after turning phi backwards (in the transverse
+// plane) from its layer-0 hit; sigma_k^2 is eq. track-error's variance at the
+// track's point of closest approach to the rough estimate, held fixed during
+// the minimisation.  Only triples whose rough estimate passes the three signal
+// tests are refined, starting from that estimate and its closest-approach
+// angles.  J has 9 - 6 = 3 degrees of freedom.
+// The minimiser is found by Levenberg-Marquardt on the nine weighted
+// residuals, with a central-difference Jacobian and a Gaussian-elimination
+// solve: slow and plain.
+// Pins: noiseless decays (exact vertex), a displaced third track against the
+// closed-form vertex of three weighted straight lines, an independent solver
+// from the same start, rotation and z-translation invariance
+// (tests/test_oracle_refine.py).
+
+// Point of track t after turning phi backwards from its layer-0 hit.
+void helix_point(const Track& t, double phi, double* p) {
+  double ps0 = std::atan2(t.h0[1] - t.cy, t.h0[0] - t.cx);
+  double ps = ps0 + (t.charge > 0 ? phi : -phi);     // backwards of a clockwise (e+) track is ccw
+  p[0] = t.cx + t.rt * std::cos(ps);
+  p[1] = t.cy + t.rt * std::sin(ps);
+  p[2] = t.h0[2] - phi * t.rbar * std::cos(t.theta1);
+}
+
+// Weighted residuals of J at x = (v, phi_0, phi_1, phi_2): r[3k + i].
+void refine_residual(const Track* T[3], const double* s2, const double* x, double* r) {
+  for (int k = 0; k < 3; ++k) {
+    double p[3];
+    helix_point(*T[k], x[3 + k], p);
+    double sk = std::sqrt(s2[k]);
+    for (int i = 0; i < 3; ++i) r[3 * k + i] = (p[i] - x[i]) / sk;
+  }
+}
+
+double sumsq9(const double* r) { double s = 0; for (int i = 0; i < 9; ++i) s += r[i] * r[i]; return s; }
+
+// Solve the n x n system A d = b in place by Gaussian elimination with
+// partial pivoting; false if A is singular.
+bool gauss_solve(double* A, double* b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r) if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double s = b[c];
+    for (int k = c + 1; k < n; ++k) s -= A[c * n + k] * b[k];
+    b[c] = s / A[c * n + c];
+  }
+  return true;
+}
+
+struct RefineOut { int status, iters; double x[6], J, s2[3]; VertexOut rough; };
+
+// status: 1 converged, 0 the rough estimate does not pass, -1 no convergence.
+RefineOut refine_triple(const Track* T[3], const Params& P) {
+  RefineOut o{};
+  o.rough = vertex_triple(T, P);
+  if (!o.rough.pass) return o;
+  double x[6] = {o.rough.x, o.rough.y, o.rough.z, 0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    const Track& t = *T[k];
+    double vx = o.rough.x - t.cx, vy = o.rough.y - t.cy, vn = std::hypot(vx, vy);
+    double cax = t.cx + t.rt * vx / vn, cay = t.cy + t.rt * vy / vn;   // closest approach
+    x[3 + k] = back_angle(t, cax, cay);
+    o.s2[k] = point_sigma2(t, cax, cay, P);
+  }
+  double r[9], J, lam = 1e-3;
+  refine_residual(T, o.s2, x, r);
+  J = sumsq9(r);
+  o.status = -1;
+  for (int it = 1; it <= 500; ++it) {
+    double Jac[9][6];
+    for (int j = 0; j < 6; ++j) {                        // central differences
+      double h = j < 3 ? 1e-6 : 1e-7, xp[6], xm[6], rp[9], rm[9];
+      for (int i = 0; i < 6; ++i) xp[i] = xm[i] = x[i];
+      xp[j] += h; xm[j] -= h;
+      refine_residual(T, o.s2, xp, rp);
+      refine_residual(T, o.s2, xm, rm);
+      for (int i = 0; i < 9; ++i) Jac[i][j] = (rp[i] - rm[i]) / (2 * h);
+    }
+    double A[36], g[6];
+    for (int a = 0; a < 6; ++a) {
+      g[a] = 0;
+      for (int i = 0; i < 9; ++i) g[a] += Jac[i][a] * r[i];
+      for (int b = 0; b < 6; ++b) {
+        double s = 0;
+        for (int i = 0; i < 9; ++i) s += Jac[i][a] * Jac[i][b];
+        A[a * 6 + b] = s;
+      }
+    }
+    bool accepted = false, tiny = false;
+    while (lam < 1e16) {
+      double M[36], d[6];
+      for (int i = 0; i < 36; ++i) M[i] = A[i];
+      for (int a = 0; a < 6; ++a) { M[a * 6 + a] *= 1 + lam; d[a] = -g[a]; }
+      if (!gauss_solve(M, d, 6)) { lam *= 10; continue; }
+      double dv = std::max({std::fabs(d[0]), std::fabs(d[1]), std::fabs(d[2])});
+      double dp = std::max({std::fabs(d[3]), std::fabs(d[4]), std::fabs(d[5])});
+      if (dv < 1e-10 && dp < 1e-12) { tiny = true; break; }   // converged: the step vanishes
+      double xn[6], rn[9];
+      for (int a = 0; a < 6; ++a) xn[a] = x[a] + d[a];
+      refine_residual(T, o.s2, xn, rn);
+      double Jn = sumsq9(rn);
+      if (Jn <= J) {
+        for (int a = 0; a < 6; ++a) x[a] = xn[a];
+        for (int i = 0; i < 9; ++i) r[i] = rn[i];
+        J = Jn;
+        lam = std::max(lam / 10, 1e-12);
+        accepted = true;
+        break;
+      }
+      lam *= 10;
+    }
+    o.iters = it;
+    if (tiny) { o.status = 1; break; }
+    if (!accepted) break;                                // no descent left but the step is not small
+  }
+  for (int a = 0; a < 6; ++a) o.x[a] = x[a];
+  o.J = J;
+  return o;
+}
+
 // ============================================================ per frame
 struct TripRec { int f, h[3]; double rtc; int pass, amb; };
 struct TrackRec { int f, h[4]; int charge; double kbar, chi2; int pass, amb; };
@@ -790,6 +928,49 @@ void oc_vertex4(const double* h, int n, const double* params, double* out) {
     o[0] = v.pass; o[1] = v.x; o[2] = v.y; o[3] = v.z; o[4] = v.chi2;
     o[5] = T[0].E + T[1].E + T[2].E; o[6] = v.amb;
     o[7] = v.dt; o[8] = v.psum; o[9] = v.reached;
+  }
+}
+
+// Refined vertex of explicit track triples given by four hits each (e+, e+,
+// e-): h [n][3][12]; out [n][16] = x, y, z, J, phi_0, phi_1, phi_2,
+// sigma2_0, sigma2_1, sigma2_2, rough x, rough y, rough z, rough chi2,
+// iterations, rough amb; status [n] = 1 converged, 0 the rough estimate does
+// not pass, -1 no convergence, -2 a track fit fails.
+void oc_refine4(const double* h, int n, const double* params, double* out, int32_t* status) {
+  Params P = unpack(params);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < n; ++i) {
+    double* o = out + 16 * i;
+    for (int k = 0; k < 16; ++k) o[k] = std::numeric_limits<double>::quiet_NaN();
+    Track T[3];
+    bool ok = true;
+    for (int k = 0; k < 3 && ok; ++k) ok = track_from_hits(h + 36 * i + 12 * k, P, T[k]);
+    if (!ok) { status[i] = -2; continue; }
+    const Track* T3[3] = {&T[0], &T[1], &T[2]};
+    RefineOut r = refine_triple(T3, P);
+    status[i] = r.status;
+    o[15] = r.rough.amb;
+    if (!r.rough.pass) continue;
+    for (int k = 0; k < 3; ++k) { o[k] = r.x[k]; o[4 + k] = r.x[3 + k]; o[7 + k] = r.s2[k]; }
+    o[3] = r.J;
+    o[10] = r.rough.x; o[11] = r.rough.y; o[12] = r.rough.z; o[13] = r.rough.chi2;
+    o[14] = r.iters;
+  }
+}
+
+// The weighted residuals of the refined-vertex objective for tracks given by
+// four hits: h [n][3][12], x [n][6] = (v, phi), s2 [n][3]; r [n][9] (NaN when
+// a track fit fails).
+void oc_refine_residual(const double* h, const double* x, const double* s2, int n, const double* params,
+                        double* r) {
+  Params P = unpack(params);
+  for (int i = 0; i < n; ++i) {
+    Track T[3];
+    bool ok = true;
+    for (int k = 0; k < 3 && ok; ++k) ok = track_from_hits(h + 36 * i + 12 * k, P, T[k]);
+    if (!ok) { for (int k = 0; k < 9; ++k) r[9 * i + k] = std::numeric_limits<double>::quiet_NaN(); continue; }
+    const Track* T3[3] = {&T[0], &T[1], &T[2]};
+    refine_residual(T3, s2 + 3 * i, x + 6 * i, r + 9 * i);
   }
 }
 

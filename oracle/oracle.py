@@ -69,6 +69,8 @@ def _bind(path: str):
     L.oc_track_geom.argtypes = [P, I, P, P, P]
     L.oc_track_point.argtypes = [P, P, I, P, P, P]
     L.oc_cone_distance.argtypes = [P, I, P, P]
+    L.oc_refine4.argtypes = [P, I, P, P, P]
+    L.oc_refine_residual.argtypes = [P, P, P, I, P, P]
     L.oc_align_loss_grad.restype = D
     L.oc_align_loss_grad.argtypes = [P, P, P, P, P, I, P, I, P, P, I, P]
     L.oc_param_count.restype = I
@@ -268,6 +270,36 @@ def cone_distance(rz: np.ndarray, params: dict):
     out = np.zeros(len(rz))
     lib().oc_cone_distance(_ptr(rz), len(rz), _ptr(pack_params(params)), _ptr(out))
     return out
+
+
+REFINE_FIELDS = ("x", "y", "z", "J", "phi0", "phi1", "phi2", "s2_0", "s2_1", "s2_2",
+                 "rough_x", "rough_y", "rough_z", "rough_chi2", "iters", "rough_amb")
+
+
+def refine4(h: np.ndarray, params: dict):
+    """Refined vertex of e+ e+ e- track triples given by four hits each (the
+    minimiser of the weighted squared distances to the three helices,
+    started from the rough estimate); h [n, 3, 4, 3] -> (out [n, 16] with
+    REFINE_FIELDS, status [n]: 1 converged, 0 rough estimate does not pass,
+    -1 no convergence, -2 a track fit fails)."""
+    h = np.ascontiguousarray(h, np.float64).reshape(-1, 36)
+    n = len(h)
+    out = np.zeros((n, 16))
+    st = np.zeros(n, np.int32)
+    lib().oc_refine4(_ptr(h), n, _ptr(pack_params(params)), _ptr(out), _ptr(st))
+    return out, st
+
+
+def refine_residual(h: np.ndarray, x: np.ndarray, s2: np.ndarray, params: dict):
+    """Weighted residuals [n, 9] of the refined-vertex objective at x [n, 6]
+    = (vertex, three turning angles) with fixed variances s2 [n, 3]."""
+    h = np.ascontiguousarray(h, np.float64).reshape(-1, 36)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
+    s2 = np.ascontiguousarray(s2, np.float64).reshape(-1, 3)
+    n = len(h)
+    r = np.zeros((n, 9))
+    lib().oc_refine_residual(_ptr(h), _ptr(x), _ptr(s2), n, _ptr(pack_params(params)), _ptr(r))
+    return r
 
 
 def align_loss_grad(fs, trip: np.ndarray, theta: np.ndarray, params: dict, grad: bool = True, weight=None):

@@ -18,7 +18,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mu3e_oracle.cpp")
 PIN_FILES = ["test_oracle_cuts.py", "test_oracle_fit.py", "test_oracle_track.py", "test_oracle_vertex.py",
-             "test_oracle_vertex_model.py", "test_oracle_grad.py"]
+             "test_oracle_vertex_model.py", "test_oracle_grad.py", "test_oracle_refine.py"]
 
 # name -> [(original text, planted text), ...]; every original occurs once.
 MUTANTS = {
@@ -86,6 +86,17 @@ MUTANTS = {
                          "chi2 += (dx * dx + dy * dy) / sg2[k];")],
     "psum_pz_with_sin": [("sz += t.p * std::cos(t.theta1);", "sz += t.p * std::sin(t.theta1);")],
     "energy_sum_two_tracks": [("double sE = A.E + B.E + C.E;", "double sE = A.E + B.E;")],
+    # Refined vertex (Section VII's more precise reconstruction)
+    "refine_helix_forward": [("double ps = ps0 + (t.charge > 0 ? phi : -phi);",
+                              "double ps = ps0 + (t.charge > 0 ? -phi : phi);")],
+    "refine_z_slope_sin": [("p[2] = t.h0[2] - phi * t.rbar * std::cos(t.theta1);",
+                            "p[2] = t.h0[2] - phi * t.rbar * std::sin(t.theta1);")],
+    "refine_weights_unsquared": [("double sk = std::sqrt(s2[k]);", "double sk = s2[k];")],
+    "refine_weights_equal": [("double sk = std::sqrt(s2[k]);", "double sk = 1.0;")],
+    "refine_sigma_at_layer0_hit": [("o.s2[k] = point_sigma2(t, cax, cay, P);",
+                                    "o.s2[k] = point_sigma2(t, t.h0[0], t.h0[1], P);")],
+    "refine_stops_early": [("if (dv < 1e-10 && dp < 1e-12) { tiny = true; break; }",
+                            "if (dv < 1e-2 && dp < 1e-3) { tiny = true; break; }")],
 }
 
 
