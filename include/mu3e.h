@@ -279,6 +279,39 @@ mu3e_status mu3e_vertex_debug(const mu3e_hits_t *hits, const mu3e_tracks_t *trac
                               size_t workspace_bytes, int32_t *triples, int32_t triple_capacity,
                               int32_t *n_triples, hipStream_t stream);
 
+/* Refined vertex of listed e+e+e- track triples: the more precise vertex
+ * reconstruction that Section VII names as the next step after the rough
+ * estimate of Section IV-C.  The refined vertex v minimises
+ *   J(v, phi) = sum_k |H_k(phi_k) - v|^2 / sigma_k^2
+ * jointly over v and one turning angle phi_k per track, H_k being track k's
+ * helix (the transverse circle of the vertex stage with the track's dip) and
+ * sigma_k^2 eq. track-error's variance at the track's closest approach to
+ * the rough estimate, held fixed; J has 3 degrees of freedom.  Only triples
+ * whose rough estimate passes the three signal tests are refined; the rough
+ * estimate is the start.  Track parameters are recomputed from the hits
+ * once per track (into the workspace, at least
+ * mu3e_vertex_workspace_size(tracks->n_tracks) bytes) and the fit runs in
+ * float64 (Gauss-Newton, at most 16 steps).
+ *   triples  [n][4]   rows {frame, a, b, c} of global track indices into
+ *                     tracks->hit (the rows mu3e_vertex_debug writes; the
+ *                     frame column is not read; tracks->frame_offsets is
+ *                     not read either)
+ *   n_valid           optional device int32: only rows [0, min(n, *n_valid))
+ *                     are processed (the count mu3e_vertex_debug writes), so
+ *                     the two calls chain without a host synchronisation;
+ *                     NULL processes all n rows.  Rows beyond are untouched.
+ *   out      [n][8]   float64: refined x, y, z (mm), J; rough x, y, z, chi2
+ *   status   [n]      the Gauss-Newton steps used (>= 1, converged); 0 the
+ *                     rough estimate does not pass (out all NaN); -1 no
+ *                     convergence (out[0..3] hold the last iterate); -2 a
+ *                     track index outside [0, n_tracks), a hit index outside
+ *                     [0, n_hits) or a failed track fit (out all NaN).
+ * Caller owns all buffers; n = 0 launches nothing.  A workspace below the
+ * size gives MU3E_ERR_CAPACITY. */
+mu3e_status mu3e_vertex_refine(const mu3e_hits_t *hits, const mu3e_tracks_t *tracks, const int32_t *triples,
+                               int32_t n, const int32_t *n_valid, const mu3e_params_t *params, double *out,
+                               int32_t *status, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ---- Chunk ingest (Section V-A) ------------------------------------------
  * A chunk is a fixed-size buffer written by the readout and copied to the
  * GPU as is (from pinned host memory, one stream per chunk in flight):

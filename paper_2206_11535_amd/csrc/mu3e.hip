@@ -1174,6 +1174,7 @@ __device__ inline bool vertex_points(const VTrack* T0, const VTrack* T1, const V
   const VTrack* tk[3] = {T0, T1, T2};
   const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
   const double lim = (double)C.r_target + (double)C.target_tol;
+#pragma unroll   // constant indices: P stays in registers
   for (int k = 0; k < 3; ++k) {
     const VTrack& A = *tk[pa[k]];
     const VTrack& B = *tk[pb[k]];
@@ -1268,7 +1269,8 @@ __device__ inline bool vertex_combo(const VTrack* T0, const VTrack* T1, const VT
 
 // All combinations of one triple in order: the passing one with the lowest
 // chi2 (the first of equal ones) in v[4].
-__device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C, double* v) {
+__device__ __forceinline__ bool vertex_triple_inline(const VTrack* T0, const VTrack* T1, const VTrack* T2,
+                                                     const Consts& C, double* v) {
   VPoints P;
   if (!vertex_points(T0, T1, T2, C, P)) return false;
   const int m = vertex_combos(P);
@@ -1281,6 +1283,158 @@ __device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* 
     }
   }
   return found;
+}
+
+__device__ bool vertex_triple(const VTrack* T0, const VTrack* T1, const VTrack* T2, const Consts& C, double* v) {
+  return vertex_triple_inline(T0, T1, T2, C, v);
+}
+
+// ================================================================ refined vertex
+// The more precise vertex reconstruction that Section VII names as the next
+// step: the point v minimising J(v, phi) = sum_k w_k |H_k(phi_k) - v|^2 jointly
+// over v and one backward turning angle phi_k per track (H_k the helix of
+// track k), with 1/w_k eq. track-error's variance at the track's closest
+// approach to the rough estimate, held fixed.  Gauss-Newton in float64 from
+// the rough estimate.  For a fixed vertex step each angle's linearised
+// optimum is explicit, so a step solves only the 3x3 system
+//   sum_k w_k (I - u_k u_k^T) dv = sum_k w_k (I - u_k u_k^T) d_k
+// (u_k the unit tangent T_k / |T_k|, d_k = H_k - v), and then
+//   dphi_k = T_k . (dv - d_k) / |T_k|^2.
+// A step that does not lower J is halved (up to kRefineHalvings times) until
+// it does, unless it is below 1e-6 mm; converged once a step is below
+// 1e-10 mm and 1e-12 rad, within kRefineIters steps (a wave runs as long as
+// its slowest lane, so both limits bound the kernel's tail).
+constexpr int kRefineIters = 16;
+constexpr int kRefineHalvings = 8;
+
+struct Helix {
+  double cx, cy, rt, ps0, q, dz, hz;   // z = hz - phi * dz
+};
+
+__device__ inline Helix helix_of(const VTrack& t) {
+  return Helix{t.cx, t.cy, t.rt, atan2(t.hy - t.cy, t.hx - t.cx), t.q, t.rbar * t.cth, t.hz};
+}
+
+// d = H(phi) - v and the tangent dH/dphi
+__device__ inline void helix_eval(const Helix& h, double phi, double vx, double vy, double vz, double* d,
+                                  double* tg) {
+  double s, c;
+  sincos(h.ps0 + h.q * phi, &s, &c);   // backwards of a clockwise (positive) track is counter-clockwise
+  d[0] = h.cx + h.rt * c - vx;
+  d[1] = h.cy + h.rt * s - vy;
+  d[2] = h.hz - phi * h.dz - vz;
+  tg[0] = -h.q * h.rt * s;
+  tg[1] = h.q * h.rt * c;
+  tg[2] = -h.dz;
+}
+
+// o[8] = refined x, y, z, J, rough x, y, z, chi2.  Returns the iterations
+// used (converged), 0 if the rough estimate does not pass, -1 if no
+// convergence within kRefineIters (o[0..3] then hold the last iterate).
+__device__ int refine_vertex(const VTrack& A, const VTrack& B, const VTrack& E, const Consts& C, double* o) {
+  double rv[4];
+  if (!vertex_triple_inline(&A, &B, &E, C, rv)) return 0;
+  o[4] = rv[0]; o[5] = rv[1]; o[6] = rv[2]; o[7] = rv[3];
+  const Helix h[3] = {helix_of(A), helix_of(B), helix_of(E)};
+  const VTrack* tk[3] = {&A, &B, &E};
+  double phi[3], w[3];
+  double vx = rv[0], vy = rv[1], vz = rv[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const VTrack& t = *tk[k];
+    const double ex = vx - t.cx, ey = vy - t.cy, en = sqrt(ex * ex + ey * ey);   // en > 0: the estimate passed
+    const double px = t.cx + t.rt * ex / en, py = t.cy + t.rt * ey / en;
+    phi[k] = back_turn(t, px, py);
+    w[k] = 1.0 / sigma2_at(t, px, py, C);
+  }
+  double d[3][3], tg[3][3], J = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    helix_eval(h[k], phi[k], vx, vy, vz, d[k], tg[k]);
+    J += w[k] * (d[k][0] * d[k][0] + d[k][1] * d[k][1] + d[k][2] * d[k][2]);
+  }
+  int status = -1;
+  for (int it = 1; it <= kRefineIters; ++it) {
+    double sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0, bx = 0, by = 0, bz = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double tt = tg[k][0] * tg[k][0] + tg[k][1] * tg[k][1] + tg[k][2] * tg[k][2];
+      const double ux = tg[k][0], uy = tg[k][1], uz = tg[k][2], wk = w[k], wt = wk / tt;
+      sxx += wk - wt * ux * ux; sxy -= wt * ux * uy; sxz -= wt * ux * uz;
+      syy += wk - wt * uy * uy; syz -= wt * uy * uz; szz += wk - wt * uz * uz;
+      const double ud = (ux * d[k][0] + uy * d[k][1] + uz * d[k][2]) * wt;
+      bx += wk * d[k][0] - ud * ux; by += wk * d[k][1] - ud * uy; bz += wk * d[k][2] - ud * uz;
+    }
+    // S^-1 b by the adjugate
+    const double a00 = syy * szz - syz * syz, a01 = sxz * syz - sxy * szz, a02 = sxy * syz - sxz * syy;
+    const double a11 = sxx * szz - sxz * sxz, a12 = sxy * sxz - sxx * syz, a22 = sxx * syy - sxy * sxy;
+    const double det = sxx * a00 + sxy * a01 + sxz * a02;
+    const double tr = sxx + syy + szz;
+    if (!(det > 1e-12 * tr * tr * tr)) break;                 // parallel tracks: no unique vertex
+    const double dvx = (a00 * bx + a01 * by + a02 * bz) / det;
+    const double dvy = (a01 * bx + a11 * by + a12 * bz) / det;
+    const double dvz = (a02 * bx + a12 * by + a22 * bz) / det;
+    double dp[3], dpmax = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double tt = tg[k][0] * tg[k][0] + tg[k][1] * tg[k][1] + tg[k][2] * tg[k][2];
+      dp[k] = (tg[k][0] * (dvx - d[k][0]) + tg[k][1] * (dvy - d[k][1]) + tg[k][2] * (dvz - d[k][2])) / tt;
+      dpmax = fmax(dpmax, fabs(dp[k]));
+    }
+    const double dvmax = fmax(fabs(dvx), fmax(fabs(dvy), fabs(dvz)));
+    if (dvmax < 1e-10 && dpmax < 1e-12) { status = it; break; }
+    // a step below 1e-6 mm is taken as it is: near the minimum the rounding
+    // of J exceeds the decrease such a step brings, and Gauss-Newton
+    // converges there without a line search
+    const bool small = dvmax < 1e-6 && dpmax < 1e-8;
+    bool accepted = false;
+    double f = 1.0;
+    for (int hv = 0; hv <= kRefineHalvings && !accepted; ++hv, f *= 0.5) {
+      double nd[3][3], nt[3][3], Jn = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        helix_eval(h[k], phi[k] + f * dp[k], vx + f * dvx, vy + f * dvy, vz + f * dvz, nd[k], nt[k]);
+        Jn += w[k] * (nd[k][0] * nd[k][0] + nd[k][1] * nd[k][1] + nd[k][2] * nd[k][2]);
+      }
+      if (Jn <= J || small) {
+        vx += f * dvx; vy += f * dvy; vz += f * dvz; J = Jn;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          phi[k] += f * dp[k];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) { d[k][i] = nd[k][i]; tg[k][i] = nt[k][i]; }
+        }
+        accepted = true;
+      }
+    }
+    if (!accepted) break;
+  }
+  o[0] = vx; o[1] = vy; o[2] = vz; o[3] = J;
+  return status;
+}
+
+// One lane per listed triple (rows {frame, a, b, c} of track indices), the
+// tracks' float64 parameters prepared once per track beforehand.
+__global__ void __launch_bounds__(256) k_refine(const VTrack* __restrict__ vt, const int32_t* __restrict__ vok,
+                                                int n_tracks, const int32_t* __restrict__ rows, int n,
+                                                const int32_t* __restrict__ n_valid, Consts C, double* out,
+                                                int32_t* status) {
+  int lim = n;
+  if (n_valid) lim = min(n, max(*n_valid, 0));
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < lim; i += gridDim.x * blockDim.x) {
+    const int a = rows[4 * (size_t)i + 1], b = rows[4 * (size_t)i + 2], e = rows[4 * (size_t)i + 3];
+    double o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = __builtin_nan("");
+    int st = -2;
+    if ((unsigned)a < (unsigned)n_tracks && (unsigned)b < (unsigned)n_tracks && (unsigned)e < (unsigned)n_tracks &&
+        vok[a] && vok[b] && vok[e])
+      st = refine_vertex(vt[a], vt[b], vt[e], C, o);
+    double* dst = out + 8 * (size_t)i;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dst[k] = o[k];
+    status[i] = st;
+  }
 }
 
 constexpr int kVtxTracks = 256;   // tracks of one frame staged in LDS for the vertex wave
@@ -2365,6 +2519,30 @@ mu3e_status mu3e_vertex_debug(const mu3e_hits_t* hits, const mu3e_tracks_t* trac
   const int g = F < cus * 16 ? F : cus * 16;
   hipLaunchKernelGGL(k_vframes_range, dim3(g), dim3(kWave), 0, stream, F, n, C, tracks->frame_offsets, vt, vok,
                      frame_flags, frame_combos, frame_vertex, TripleRec{triples, n_triples, triple_capacity});
+  return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
+}
+
+mu3e_status mu3e_vertex_refine(const mu3e_hits_t* hits, const mu3e_tracks_t* tracks, const int32_t* triples,
+                               int32_t n, const int32_t* n_valid, const mu3e_params_t* params, double* out,
+                               int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!hits || hits->n_hits < 0 || !tracks || tracks->n_tracks < 0 || n < 0 || !params) return MU3E_ERR_INVALID_ARG;
+  Consts C;
+  if (!make_consts(params, C)) return MU3E_ERR_INVALID_ARG;
+  if (n == 0) return MU3E_OK;
+  const int nt = tracks->n_tracks;
+  if (!triples || !out || !status || (nt > 0 && (!tracks->hit || !hits->x || !hits->y || !hits->z)))
+    return MU3E_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < mu3e_vertex_workspace_size(nt)) return MU3E_ERR_CAPACITY;
+  VTrack* vt = static_cast<VTrack*>(workspace);
+  int32_t* vok = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + align256((size_t)nt * sizeof(VTrack)));
+  const int cus = device_cus();
+  if (nt > 0) {
+    const int b = (nt + 255) / 256 < cus * 8 ? (nt + 255) / 256 : cus * 8;
+    hipLaunchKernelGGL(k_vprep_range, dim3(b), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->n_hits, C,
+                       tracks->hit, nt, vt, vok);
+  }
+  const int blocks = (n + 255) / 256 < cus * 8 ? (n + 255) / 256 : cus * 8;
+  hipLaunchKernelGGL(k_refine, dim3(blocks), dim3(256), 0, stream, vt, vok, nt, triples, n, n_valid, C, out, status);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 

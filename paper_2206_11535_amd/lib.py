@@ -131,6 +131,9 @@ def declare(L):
     L.mu3e_vertex_debug.restype = ctypes.c_int
     L.mu3e_vertex_debug.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Tracks), ctypes.POINTER(Params), P, P, P,
                                     P, Z, P, I, P, P]
+    L.mu3e_vertex_refine.restype = ctypes.c_int
+    L.mu3e_vertex_refine.argtypes = [ctypes.POINTER(Hits), ctypes.POINTER(Tracks), P, I, P, ctypes.POINTER(Params),
+                                     P, P, P, Z, P]
     L.mu3e_plan_create.restype = ctypes.c_int
     L.mu3e_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Hits), ctypes.POINTER(Params),
                                    P, P, P, P, Z, I, I, ctypes.POINTER(Tuning)]
@@ -613,6 +616,36 @@ def vertex(hits: DeviceHits, track_hits, frame_offsets, params: dict, stream=Non
                                _stream(stream)), "mu3e_vertex_debug")
     m = int(nrow.item())
     return flags[:F], combos[:F], vtx[:F], rows[:min(m, int(triple_capacity))], m
+
+
+REFINE_FIELDS = ("x", "y", "z", "J", "rough_x", "rough_y", "rough_z", "rough_chi2")
+
+
+def vertex_refine(hits: DeviceHits, track_hits, rows, params: dict, n_valid=None, stream=None):
+    """Refined vertex of listed e+e+e- track triples (mu3e_vertex_refine):
+    track_hits int32 [n_tracks, 4], rows int32 [n, 4] {frame, a, b, c} (the
+    rows vertex(..., triple_capacity) returns), optional n_valid (an int32
+    cuda tensor [1] bounding the rows read) -> (out float64 [n, 8] with
+    REFINE_FIELDS, status int32 [n]: steps used, 0 no rough vertex, -1 no
+    convergence, -2 invalid track)."""
+    import torch
+    L = load()
+    track_hits = _dev(track_hits, torch.int32, (4,), "track_hits")
+    rows = _dev(rows, torch.int32, (4,), "rows")
+    if n_valid is not None:
+        n_valid = _dev(n_valid, torch.int32, (), "n_valid")
+    n, nt = int(rows.shape[0]), int(track_hits.shape[0])
+    dev = rows.device
+    out = torch.full((max(n, 1), 8), float("nan"), dtype=torch.float64, device=dev)
+    status = torch.full((max(n, 1),), -3, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(L.mu3e_vertex_workspace_size(nt), 256), dtype=torch.uint8, device=dev)
+    hs = hits.struct()
+    tr = Tracks(track_hits.data_ptr() if nt else None, None, 0, nt)
+    pp = make_params(params)
+    _check(L.mu3e_vertex_refine(ctypes.byref(hs), ctypes.byref(tr), _ptr(rows) if n else None, n,
+                                _ptr(n_valid) if n_valid is not None else None, ctypes.byref(pp), _ptr(out),
+                                _ptr(status), _ptr(ws), ws.numel(), _stream(stream)), "mu3e_vertex_refine")
+    return out[:n], status[:n]
 
 
 def align_chi2(hits: DeviceHits, trip, theta, params: dict, stream=None):

@@ -86,6 +86,19 @@ def test_host_validation(L):
     assert L.mu3e_vertex(ctypes.byref(h), None, ctypes.byref(p), 1, 1, 1, 1, 1 << 20, None) == -1
     tr = lib.Tracks(80, 96, 4, 1000)
     assert L.mu3e_vertex(ctypes.byref(h), ctypes.byref(tr), ctypes.byref(p), 1, 1, 1, 1, 8, None) == -3
+    # refined vertex: null rows or outputs, negative count, too small workspace
+    tr = lib.Tracks(80, 96, 4, 1000)
+    assert L.mu3e_vertex_refine(ctypes.byref(h), ctypes.byref(tr), None, 5, None, ctypes.byref(p), 1, 1, 1,
+                                1 << 20, None) == -1
+    assert L.mu3e_vertex_refine(ctypes.byref(h), ctypes.byref(tr), 1, -1, None, ctypes.byref(p), 1, 1, 1,
+                                1 << 20, None) == -1
+    assert L.mu3e_vertex_refine(ctypes.byref(h), ctypes.byref(tr), 1, 5, None, ctypes.byref(p), None, 1, 1,
+                                1 << 20, None) == -1
+    assert L.mu3e_vertex_refine(ctypes.byref(h), None, 1, 5, None, ctypes.byref(p), 1, 1, 1, 1 << 20, None) == -1
+    assert L.mu3e_vertex_refine(ctypes.byref(h), ctypes.byref(tr), 1, 5, None, ctypes.byref(p), 1, 1, 1, 8,
+                                None) == -3
+    assert L.mu3e_vertex_refine(ctypes.byref(h), ctypes.byref(tr), None, 0, None, ctypes.byref(p), None, None,
+                                None, 0, None) == 0
     # triplet capacity beyond 2^30
     assert L.mu3e_select_workspace_size(10, (1 << 30) + 1, 10) == 0
     assert L.mu3e_select_frames(ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, (1 << 30) + 1, 10, None,
@@ -118,6 +131,8 @@ def test_host_validation(L):
     assert L.mu3e_vertex(ctypes.byref(hn), ctypes.byref(lib.Tracks(80, 96, 4, 10)), ctypes.byref(p), 1, 1, 1, 1,
                          1 << 20, None) == -1
     assert L.mu3e_align_chi2(ctypes.byref(hn), 1, 5, 1, 8, ctypes.byref(p), 1, None) == -1
+    assert L.mu3e_vertex_refine(ctypes.byref(hn), ctypes.byref(lib.Tracks(80, 96, 4, 10)), 1, 5, None,
+                                ctypes.byref(p), 1, 1, 1, 1 << 20, None) == -1
     assert L.mu3e_align_backward(ctypes.byref(hn), 1, 5, 1, 8, ctypes.byref(p), 1, 1, 1, sens, None) == -1
     assert L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(hn), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10,
                               None) == -1

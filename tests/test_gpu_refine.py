@@ -1,0 +1,198 @@
+"""Parity of the refined vertex fit (mu3e_vertex_refine, through the C ABI)
+with the oracle's refined vertex (a plain Levenberg-Marquardt minimiser of
+the same objective, started from the same rough estimate).
+
+Both sides run in float64 on the same float32 hits.  Compared on every row
+whose rough estimate the oracle does not mark ambiguous:
+* the outcome class exactly: refined (converged or not), no passing rough
+  estimate, invalid track;
+* on rows both sides refine to convergence: the vertex within 1e-6 mm, J
+  within 1e-7 relative, the rough estimate within 1e-7 mm and its chi2
+  within 1e-9 relative (the minimiser is unique near the start; the two
+  solvers stop at steps below 1e-10 mm, and the remaining difference is the
+  rounding of two float64 track refits amplified by the conditioning);
+* rows either side leaves unconverged stay below 1 %.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2206_11535_amd import synth
+from paper_2206_11535_amd.params import default_params, lifted_caps
+from helpers import helix_hits
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_11535_amd import lib as L
+    L.load()
+    return L
+
+
+def compare(go, gs, oo, ost, what):
+    go, gs = go.cpu().numpy(), gs.cpu().numpy()
+    keep = oo[:, 15] != 1
+    cg = np.where(gs >= 1, 1, gs)
+    conv_o = ost == 1
+    refined_g = (cg == 1) | (cg == -1)
+    refined_o = (ost == 1) | (ost == -1)
+    assert np.array_equal(refined_g[keep], refined_o[keep]), what
+    assert np.array_equal((cg == 0)[keep], (ost == 0)[keep]), what
+    assert np.array_equal((cg == -2)[keep], (ost == -2)[keep]), what
+    both = keep & (cg == 1) & conv_o
+    either = keep & refined_o & ~((cg == 1) & conv_o)
+    n_ref = int((keep & refined_o).sum())
+    dv = np.abs(go[both, :3] - oo[both, :3]).max(initial=0.0)
+    dj = (np.abs(go[both, 3] - oo[both, 3]) / (1 + oo[both, 3])).max(initial=0.0)
+    dr = np.abs(go[both, 4:7] - oo[both, 10:13]).max(initial=0.0)
+    dc = (np.abs(go[both, 7] - oo[both, 13]) / (1 + oo[both, 13])).max(initial=0.0)
+    print(f"{what}: {len(gs)} rows, {int(keep.sum())} unambiguous, {n_ref} refined, {int(both.sum())} compared, "
+          f"{int(either.sum())} unconverged on a side; max |dv| {dv:.3g} mm, dJ {dj:.3g}, rough {dr:.3g} mm, "
+          f"rough chi2 {dc:.3g}; GPU steps median {np.median(gs[gs >= 1]) if (gs >= 1).any() else 0}", flush=True)
+    assert either.sum() <= 0.01 * max(n_ref, 1), what
+    assert dv <= 1e-6 and dj <= 1e-7 and dr <= 1e-7 and dc <= 1e-9, what
+    # rows outside [0, n_valid) or whose class is not refined hold NaN
+    assert np.isnan(go[(cg == 0) | (cg == -2)]).all()
+    return int(both.sum())
+
+
+def decay_frames(n, seed, ms=True, quant=True):
+    """Signal decays, one frame each (3 hits per layer): the FrameSet and the
+    global hit indices of the three tracks [m, 3, 4] (e+, e+, e-)."""
+    rng = np.random.default_rng(seed)
+    mom = synth.sample_signal(rng, n)
+    v = synth.sample_target(rng, n)
+    hs = []
+    for k in range(n):
+        h = helix_hits(np.repeat(v[k][None], 3, 0), mom[k], [1, -1, 1], ms=ms, quant=quant, accept=False,
+                       rng=rng)
+        if np.all(np.isfinite(h)):
+            hs.append(h[[0, 2, 1]])
+    H = np.array(hs)                            # [m, 3 tracks, 4 layers, 3]
+    m = len(H)
+    xyz = H.transpose(0, 2, 1, 3).reshape(-1, 3)  # frame, layer, track
+    lay = np.tile(np.repeat(np.arange(4), 3), m)
+    lo = np.arange(0, 12 * m + 1, 3, dtype=np.int32)
+    n_hits = len(xyz)
+    fs = synth.FrameSet(xyz[:, 0].astype(np.float32), xyz[:, 1].astype(np.float32), xyz[:, 2].astype(np.float32),
+                        lay.astype(np.uint16), np.zeros(n_hits, np.uint16), lo, np.full(n_hits, -1, np.int32), {},
+                        np.zeros(m, bool))
+    idx = (12 * np.arange(m)[:, None, None] + 3 * np.arange(4)[None, None, :] + np.arange(3)[None, :, None])
+    return fs, idx.astype(np.int32)
+
+
+def hits_of(fs, idx):
+    """float64 copies of the float32 hits at idx [..., 4] -> [..., 4, 3]."""
+    return np.stack([fs.x[idx], fs.y[idx], fs.z[idx]], -1).astype(np.float64)
+
+
+def test_signal_decays_equal_oracle(lib):
+    import torch
+    for ms, quant in ((True, True), (False, False)):
+        fs, idx = decay_frames(600, 31 + ms, ms=ms, quant=quant)
+        m = len(idx)
+        print(f"case: {m} signal decays, ms {ms}, quantised {quant}", flush=True)
+        dh = lib.to_device(fs)
+        th = idx.reshape(-1, 4)
+        rows = np.stack([np.arange(m), 3 * np.arange(m), 3 * np.arange(m) + 1, 3 * np.arange(m) + 2], 1)
+        go, gs = lib.vertex_refine(dh, torch.from_numpy(th).cuda(), torch.from_numpy(rows.astype(np.int32)).cuda(),
+                                   default_params())
+        torch.cuda.synchronize()
+        oo, ost = oracle.refine4(hits_of(fs, idx), default_params())
+        n = compare(go, gs, oo, ost, f"decays ms={ms} quant={quant}")
+        assert n > 0.6 * m
+        if not ms:
+            # noiseless: the exact vertex up to the float32 rounding of the hits
+            assert (gs.cpu().numpy() >= 1).all()
+
+
+def gpu_triples(lib, fs, p):
+    """The GPU's accepted tracks and its energy-passing triples (rows of
+    mu3e_vertex_debug) for a batch."""
+    import torch
+    dh = lib.to_device(fs)
+    sel = lib.select_frames(dh, p)
+    torch.cuda.synchronize()
+    _, tracks, kf, c = sel.lists(fs.layer_offsets)
+    assert c[2] == 0
+    order = np.lexsort((tracks[:, 3], tracks[:, 2], tracks[:, 1], tracks[:, 0]))
+    tracks = tracks[order]
+    F = fs.n_frames
+    off = np.searchsorted(tracks[:, 0], np.arange(F + 1)).astype(np.int32)
+    th = np.ascontiguousarray(tracks[:, 1:5], dtype=np.int32)
+    th_d = torch.from_numpy(th).cuda()
+    _, _, _, rows, m = lib.vertex(dh, th_d, torch.from_numpy(off).cuda(), p, triple_capacity=2_000_000)
+    assert m == len(rows)
+    return dh, th, th_d, rows
+
+
+def test_energy_passing_triples_equal_oracle(lib):
+    """Every e+e+e- triple of the GPU's own tracks that passes the energy
+    test, on a batch with many signal frames: refined on the GPU and by the
+    oracle from the same hits."""
+    import torch
+    cfg = dataclasses.replace(synth.CONFIGS[2], lam=12.0, signal_frac=0.3)
+    fs = synth.generate(cfg, n_frames=1500, salt=23)
+    p = lifted_caps()
+    dh, th, th_d, rows = gpu_triples(lib, fs, p)
+    m = len(rows)
+    print(f"case: {m} energy-passing triples of {len(th)} tracks", flush=True)
+    assert m > 500
+    go, gs = lib.vertex_refine(dh, th_d, rows, p)
+    torch.cuda.synchronize()
+    r = rows.cpu().numpy()
+    oo, ost = oracle.refine4(hits_of(fs, th[r[:, 1:4]]), p)
+    n = compare(go, gs, oo, ost, "energy-passing triples")
+    assert n > 100
+
+
+def test_chained_count_bounds_rows(lib):
+    """n_valid (a device count, as mu3e_vertex_debug writes it) bounds the
+    rows read; rows beyond it are left untouched; a count above n reads n."""
+    import torch
+    fs, idx = decay_frames(200, 41)
+    m = len(idx)
+    dh = lib.to_device(fs)
+    th = torch.from_numpy(idx.reshape(-1, 4)).cuda()
+    rows = torch.from_numpy(np.stack([np.arange(m), 3 * np.arange(m), 3 * np.arange(m) + 1,
+                                      3 * np.arange(m) + 2], 1).astype(np.int32)).cuda()
+    p = default_params()
+    full, fst = lib.vertex_refine(dh, th, rows, p)
+    half = torch.tensor([m // 2], dtype=torch.int32, device="cuda")
+    part, pst = lib.vertex_refine(dh, th, rows, p, n_valid=half)
+    over = torch.tensor([m + 50], dtype=torch.int32, device="cuda")
+    allr, ast = lib.vertex_refine(dh, th, rows, p, n_valid=over)
+    torch.cuda.synchronize()
+    k = m // 2
+    assert torch.equal(pst[:k], fst[:k]) and torch.equal(ast, fst)
+    assert torch.equal(torch.nan_to_num(part[:k], nan=-1.0), torch.nan_to_num(full[:k], nan=-1.0))
+    assert (pst[k:] == -3).all() and torch.isnan(part[k:]).all()      # the binding's fill, untouched
+
+
+def test_invalid_rows_and_tracks(lib):
+    import torch
+    fs, idx = decay_frames(20, 42, ms=False, quant=False)
+    m = len(idx)
+    th = idx.reshape(-1, 4).copy()
+    th[3, 2] = fs.n_hits + 5                    # track 3: a hit index beyond the hits
+    rows = np.stack([np.arange(m), 3 * np.arange(m), 3 * np.arange(m) + 1, 3 * np.arange(m) + 2], 1)
+    rows[0, 2] = len(th)                         # row 0: a track index beyond the tracks
+    rows[2, 3] = -1                              # row 2: negative
+    dh = lib.to_device(fs)
+    go, gs = lib.vertex_refine(dh, torch.from_numpy(th).cuda(), torch.from_numpy(rows.astype(np.int32)).cuda(),
+                               default_params())
+    torch.cuda.synchronize()
+    gs = gs.cpu().numpy()
+    assert gs[0] == -2 and gs[1] == -2 and gs[2] == -2     # row 1 holds track 3
+    assert (gs[3:] >= 1).all()
+    assert np.isnan(go.cpu().numpy()[:3]).all()
+    e, es = lib.vertex_refine(dh, torch.from_numpy(th).cuda(), torch.zeros((0, 4), dtype=torch.int32).cuda(),
+                              default_params())
+    assert e.shape == (0, 8) and es.shape == (0,)

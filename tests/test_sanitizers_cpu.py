@@ -135,6 +135,10 @@ checks.append(L.mu3e_vertex(ctypes.byref(h), None, ctypes.byref(p), 1, 1, 1, 1, 
 tr = Tracks(80, 96, 4, 1000)
 checks.append(L.mu3e_vertex(ctypes.byref(h), ctypes.byref(tr), ctypes.byref(p), 1, 1, 1, 1, 8, None) == -3)
 checks.append(L.mu3e_align_chi2(ctypes.byref(hn), 1, 5, 1, 8, ctypes.byref(p), 1, None) == -1)
+checks.append(L.mu3e_vertex_refine(ctypes.byref(h), ctypes.byref(tr), 1, 5, None, ctypes.byref(p), 1, 1, 1, 8,
+                                   None) == -3)
+checks.append(L.mu3e_vertex_refine(ctypes.byref(hn), ctypes.byref(tr), 1, 5, None, ctypes.byref(p), 1, 1, 1,
+                                   1 << 20, None) == -1)
 t = Tuning(8, 4, 0, 101, 64, 1)
 plan = ctypes.c_void_p()
 checks.append(L.mu3e_plan_create(ctypes.byref(plan), ctypes.byref(h), ctypes.byref(p), 1, 1, 1, 1, 1 << 30, 10, 10,
