@@ -2034,8 +2034,18 @@ __global__ void __launch_bounds__(256)
 k_align_fwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
             const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
             const float* __restrict__ theta, int n_sensors, Consts C, float* __restrict__ chi2) {
+  extern __shared__ double strig[];   // cos, sin of each sensor's angle, once per block
+  for (int j = threadIdx.x; j < n_sensors; j += blockDim.x) align_trig(theta, j, strig);
+  __syncthreads();
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    chi2[t] = align_chi2_one(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, C);
+    chi2[t] = align_chi2_one(X, Y, Z, S, n_hits, n_sensors, theta, strig, trip + 3 * t, C);
+}
+
+// cos, sin of each sensor's angle for the backward pass (into the workspace).
+__global__ void __launch_bounds__(256) k_align_trig(const float* __restrict__ theta, int n_sensors,
+                                                    double* __restrict__ trig) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_sensors; j += gridDim.x * blockDim.x)
+    align_trig(theta, j, trig);
 }
 
 // Per block: sum over its triplets of grad_chi2[t] d chi2_t / d theta into
@@ -2043,8 +2053,8 @@ k_align_fwd(const float* __restrict__ X, const float* __restrict__ Y, const floa
 __global__ void __launch_bounds__(256)
 k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
             const uint16_t* __restrict__ S, int n_hits, const int32_t* __restrict__ trip, int n,
-            const float* __restrict__ theta, int n_sensors, Consts C, const float* __restrict__ gchi2,
-            double* __restrict__ partial) {
+            const float* __restrict__ theta, const double* __restrict__ trig, int n_sensors, Consts C,
+            const float* __restrict__ gchi2, double* __restrict__ partial) {
   extern __shared__ double acc[];   // 4 * n_sensors float64 accumulators
   const int np = 4 * n_sensors;
   for (int j = threadIdx.x; j < np; j += blockDim.x) acc[j] = 0.0;
@@ -2052,7 +2062,7 @@ k_align_bwd(const float* __restrict__ X, const float* __restrict__ Y, const floa
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     double gs[12];
     int s[3];
-    if (!align_grad_one(X, Y, Z, S, n_hits, n_sensors, theta, trip + 3 * t, C, gchi2[t], s, gs)) continue;
+    if (!align_grad_one(X, Y, Z, S, n_hits, n_sensors, theta, trig, trip + 3 * t, C, gchi2[t], s, gs)) continue;
     for (int k = 0; k < 3; ++k) {
       double* a = acc + 4 * s[k];
       atomicAdd(a + 0, gs[4 * k]);
@@ -2569,9 +2579,10 @@ mu3e_status mu3e_fit_triplets_backward(const mu3e_hits_t* hits, const int32_t* t
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
-// Workspace of mu3e_align_backward: the per-block rows and the group sums.
+// Workspace of mu3e_align_backward: the per-block rows, the group sums and
+// the sensors' cos, sin table.
 struct AlignLayout {
-  size_t partial, part2, total;
+  size_t partial, part2, trig, total;
 };
 
 static AlignLayout align_layout(int n_sensors) {
@@ -2579,7 +2590,8 @@ static AlignLayout align_layout(int n_sensors) {
   AlignLayout L;
   L.partial = 0;
   L.part2 = align256((size_t)kAlignBlocks * np * sizeof(double));
-  L.total = L.part2 + align256((size_t)kAlignGroups * np * sizeof(double));
+  L.trig = L.part2 + align256((size_t)kAlignGroups * np * sizeof(double));
+  L.total = L.trig + align256(2 * (size_t)n_sensors * sizeof(double));
   return L;
 }
 
@@ -2602,9 +2614,11 @@ mu3e_status mu3e_align_chi2(const mu3e_hits_t* hits, const int32_t* trip, int32_
   if (n_sensors > kAlignMaxSensors) return MU3E_ERR_UNSUPPORTED;
   if (n == 0) return MU3E_OK;
   const int cus = device_cus();
-  const int b = (n + 255) / 256 < cus * 8 ? (n + 255) / 256 : cus * 8;
-  hipLaunchKernelGGL(k_align_fwd, dim3(b), dim3(256), 0, stream, hits->x, hits->y, hits->z, hits->sensor,
-                     hits->n_hits, trip, n, theta, n_sensors, C, chi2);
+  // four blocks per compute unit: each block computes the sensor table once
+  // and then takes several triplets per lane
+  const int b = (n + 255) / 256 < cus * 4 ? (n + 255) / 256 : cus * 4;
+  hipLaunchKernelGGL(k_align_fwd, dim3(b), dim3(256), 2 * (size_t)n_sensors * sizeof(double), stream, hits->x,
+                     hits->y, hits->z, hits->sensor, hits->n_hits, trip, n, theta, n_sensors, C, chi2);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;
 }
 
@@ -2621,10 +2635,16 @@ mu3e_status mu3e_align_backward(const mu3e_hits_t* hits, const int32_t* trip, in
   char* ws = static_cast<char*>(workspace);
   double* partial = reinterpret_cast<double*>(ws + AL.partial);
   double* part2 = reinterpret_cast<double*>(ws + AL.part2);
+  double* trig = reinterpret_cast<double*>(ws + AL.trig);
   const int np = 4 * n_sensors;
   const int ncb = (np + kWave - 1) / kWave;
+  // the sensors' cos, sin table once into the workspace (in each block's LDS
+  // beside the accumulators it lowers the occupancy and ran slower); none
+  // without triplets: theta may then be NULL, and the gradient is zero
+  if (n > 0)
+    hipLaunchKernelGGL(k_align_trig, dim3((n_sensors + 255) / 256), dim3(256), 0, stream, theta, n_sensors, trig);
   hipLaunchKernelGGL(k_align_bwd, dim3(kAlignBlocks), dim3(256), (size_t)np * sizeof(double), stream, hits->x, hits->y,
-                     hits->z, hits->sensor, hits->n_hits, trip, n, theta, n_sensors, C, grad_chi2, partial);
+                     hits->z, hits->sensor, hits->n_hits, trip, n, theta, trig, n_sensors, C, grad_chi2, partial);
   hipLaunchKernelGGL(k_align_reduce, dim3(ncb, kAlignGroups), dim3(256), 0, stream, partial, kAlignBlocks, np, part2);
   hipLaunchKernelGGL(k_align_reduce2, dim3((np + 255) / 256), dim3(256), 0, stream, part2, np, grad_theta);
   return hipGetLastError() == hipSuccess ? MU3E_OK : MU3E_ERR_HIP;

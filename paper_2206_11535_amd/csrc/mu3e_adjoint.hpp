@@ -217,13 +217,21 @@ __host__ __device__ inline bool fit_chi2_adjoint(const double* h, const Consts& 
 // ------------------------------------------------------------- alignment
 // theta[s] = (tx, ty, tz, alpha) of sensor s moves a hit to
 // R_z(alpha) (x, y, z) + (tx, ty, tz).  Coordinates after alignment are
-// formed in float64.
+// formed in float64.  trig[2s], trig[2s + 1] = cos, sin of (double)alpha_s,
+// computed once per sensor by the caller (align_trig).
+__host__ __device__ inline void align_trig(const float* theta, int s, double* trig) {
+  const double a = theta[4 * s + 3];
+  trig[2 * s] = cos(a);
+  trig[2 * s + 1] = sin(a);
+}
+
 __host__ __device__ inline void align_hit(const float* X, const float* Y, const float* Z, const uint16_t* S,
-                                          const float* theta, int g, double* h, int& s, double& ca, double& sa) {
+                                          const float* theta, const double* trig, int g, double* h, int& s,
+                                          double& ca, double& sa) {
   s = S[g];
-  const double tx = theta[4 * s], ty = theta[4 * s + 1], tz = theta[4 * s + 2], a = theta[4 * s + 3];
-  ca = cos(a);
-  sa = sin(a);
+  const double tx = theta[4 * s], ty = theta[4 * s + 1], tz = theta[4 * s + 2];
+  ca = trig[2 * s];
+  sa = trig[2 * s + 1];
   const double x = X[g], y = Y[g];
   h[0] = ca * x - sa * y + tx;
   h[1] = sa * x + ca * y + ty;
@@ -233,24 +241,24 @@ __host__ __device__ inline void align_hit(const float* X, const float* Y, const 
 // The three aligned hits of triplet tr (global hit indices); false if an
 // index or a sensor id is out of range.
 __host__ __device__ inline bool align_triplet(const float* X, const float* Y, const float* Z, const uint16_t* S,
-                                              int n_hits, int n_sensors, const float* theta, const int32_t* tr,
-                                              double* h, int* s, double* ca, double* sa) {
+                                              int n_hits, int n_sensors, const float* theta, const double* trig,
+                                              const int32_t* tr, double* h, int* s, double* ca, double* sa) {
   for (int k = 0; k < 3; ++k) {
     const int g = tr[k];
     if ((unsigned)g >= (unsigned)n_hits) return false;
     if (S[g] >= n_sensors) return false;
-    align_hit(X, Y, Z, S, theta, g, h + 3 * k, s[k], ca[k], sa[k]);
+    align_hit(X, Y, Z, S, theta, trig, g, h + 3 * k, s[k], ca[k], sa[k]);
   }
   return true;
 }
 
 // chi2 of one triplet after alignment (float32 fit); NaN if degenerate.
 __host__ __device__ inline float align_chi2_one(const float* X, const float* Y, const float* Z, const uint16_t* S,
-                                                int n_hits, int n_sensors, const float* theta, const int32_t* tr,
-                                                const Consts& C) {
+                                                int n_hits, int n_sensors, const float* theta,
+                                                const double* trig, const int32_t* tr, const Consts& C) {
   double h[9], ca[3], sa[3];
   int s[3];
-  if (!align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, tr, h, s, ca, sa)) return __builtin_nanf("");
+  if (!align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, trig, tr, h, s, ca, sa)) return __builtin_nanf("");
   const Fit<float> f = fit_triplet<float>(h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], h[8], C);
   return f.ok ? f.chi2 : __builtin_nanf("");
 }
@@ -258,10 +266,11 @@ __host__ __device__ inline float align_chi2_one(const float* X, const float* Y, 
 // w * d chi2 / d theta of one triplet: gs[4k..4k+3] for the sensor s[k] of
 // hit k.  False (nothing to add) if the triplet is degenerate.
 __host__ __device__ inline bool align_grad_one(const float* X, const float* Y, const float* Z, const uint16_t* S,
-                                               int n_hits, int n_sensors, const float* theta, const int32_t* tr,
-                                               const Consts& C, float w, int* s, double* gs) {
+                                               int n_hits, int n_sensors, const float* theta,
+                                               const double* trig, const int32_t* tr, const Consts& C, float w,
+                                               int* s, double* gs) {
   double h[9], ca[3], sa[3];
-  if (!align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, tr, h, s, ca, sa)) return false;
+  if (!align_triplet(X, Y, Z, S, n_hits, n_sensors, theta, trig, tr, h, s, ca, sa)) return false;
   double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   float c;
   if (!fit_chi2_adjoint<float>(h, C, w, c, g)) return false;

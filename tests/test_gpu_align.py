@@ -195,9 +195,9 @@ def test_invalid_indices_and_sensors(setup):
 
 def test_gradient_deterministic_and_reused_workspace(setup):
     """The backward pass sums in a fixed order (per-block rows, then group
-    sums, then their sum by the last block of each column group): repeated
-    calls, also on one workspace reused across calls and with another
-    triplet set in between, give bitwise the same gradient."""
+    sums, then the sum of the group sums): repeated calls, also on one
+    workspace reused across calls and with another triplet set in between,
+    give bitwise the same gradient."""
     import torch
     lib, fs, p, trip, dh = setup
     S = synth.N_SENSORS
@@ -210,3 +210,28 @@ def test_gradient_deterministic_and_reused_workspace(setup):
     c = lib.align_backward(dh, tt, th, p, g).cpu().numpy()
     assert np.array_equal(a, b) and np.array_equal(a, c)
     assert np.count_nonzero(a) > 1000
+
+
+def test_padded_sensor_table(setup):
+    """Padding theta with unused sensors (2000 in all) leaves the chi2 and
+    the gradient of the sensors in use unchanged and gives the unused ones a
+    zero gradient (the sensors' cos, sin tables and the accumulators are
+    indexed by sensor)."""
+    import torch
+    lib, fs, p, trip, dh = setup
+    S = synth.N_SENSORS
+    rng = np.random.default_rng(5)
+    theta = np.concatenate([rng.normal(0, 0.02, (S, 3)), rng.normal(0, 2e-4, (S, 1))], 1).astype(np.float32)
+    big = np.zeros((2000, 4), np.float32)
+    big[:S] = theta
+    tt = torch.from_numpy(trip).cuda()
+    g = torch.ones(len(trip), dtype=torch.float32, device="cuda")
+    ts, tb = torch.from_numpy(theta).cuda(), torch.from_numpy(big).cuda()
+    a = lib.align_backward(dh, tt, ts, p, g).cpu().numpy()
+    b = lib.align_backward(dh, tt, tb, p, g).cpu().numpy()
+    assert np.count_nonzero(a) > 1000
+    assert not np.any(b[S:])
+    np.testing.assert_allclose(b[:S], a, rtol=1e-6, atol=1e-9 * np.abs(a).max())
+    ca = lib.align_chi2(dh, tt, ts, p).cpu().numpy()
+    cb = lib.align_chi2(dh, tt, tb, p).cpu().numpy()
+    assert np.array_equal(ca, cb)
