@@ -65,7 +65,8 @@ constexpr int kTallyOffset = 512;            // selected-triplet tallies: claims
 // than slots, [5] entries queued for the
 // float64 re-evaluation, [7] triplet-list entries handed out in chunks
 // (also past the capacity: each grant adds one chunk), [9] and [10] lengths
-// of the slice tables
+// of the slice tables, [12] frames deferred to k_tiles, [13] their claims,
+// [16] claims of the vertex stage's candidate frames
 enum { ST_TRIP_FULL = 1, ST_TRACK_FULL = 2, ST_BAD_OFFSETS = 4 };
 
 // Value of lane k (uniform k) in every lane: one v_readlane, no LDS crossbar.
@@ -1205,6 +1206,24 @@ __device__ inline bool vertex_points(const VTrack* T0, const VTrack* T1, const V
   return true;
 }
 
+// Whether the circles of tracks A and B may have an intersection near the
+// target, as vertex_points decides it for the pair (A, B), with margins
+// (1e-12 relative on the circle test, 1e-6 on the squared target radius,
+// which covers the rounding of the intersection points even near tangency)
+// so that it never rejects a pair that vertex_points accepts: a prefilter.
+__device__ inline bool pair_may_meet(const VTrack& A, const VTrack& B, double lim2) {
+  const double dx = B.cx - A.cx, dy = B.cy - A.cy;
+  const double d = sqrt(dx * dx + dy * dy);
+  if (d == 0.0 || d > (A.rt + B.rt) * (1.0 + 1e-12) || d < fabs(A.rt - B.rt) * (1.0 - 1e-12)) return false;
+  const double a = (A.rt * A.rt - B.rt * B.rt + d * d) / (2.0 * d);
+  const double h = sqrt(fmax(A.rt * A.rt - a * a, 0.0));
+  const double ux = dx / d, uy = dy / d;
+  const double x0 = A.cx + a * ux + h * uy, y0 = A.cy + a * uy - h * ux;
+  const double x1 = A.cx + a * ux - h * uy, y1 = A.cy + a * uy + h * ux;
+  const double l2 = lim2 * (1.0 + 1e-6);
+  return x0 * x0 + y0 * y0 <= l2 || x1 * x1 + y1 * y1 <= l2;
+}
+
 // Bit c of the mask: combination c (intersection c & 1 of pair 0, (c >> 1) & 1
 // of pair 1, (c >> 2) & 1 of pair 2) exists.
 __device__ inline int vertex_combos(const VPoints& P) {
@@ -1438,6 +1457,8 @@ __global__ void __launch_bounds__(256) k_refine(const VTrack* __restrict__ vt, c
 }
 
 constexpr int kVtxTracks = 256;   // tracks of one frame staged in LDS for the vertex wave
+constexpr int kPairWords = 64;    // pair-prefilter bits per frame: 64 x 64 (512 B of LDS)
+constexpr int kPairFilterMin = 512;   // triples of a frame from which the prefilter pays
 
 // Vertex stage of one frame by one wave (Alg. 4): tracks split by charge,
 // lanes over the flat index of e+e+e- triples (unordered e+ pair, e-) for
@@ -1524,9 +1545,7 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
   // flat triple index k -> (e+ i, e+ j > i, e- e): k = pair * nn + e, pairs in
   // row-major order (row i holds np - 1 - i pairs and starts at
   // i (2 np - i - 1) / 2), the row found by the quadratic formula and corrected
-  auto decode = [&](int k, int& i, int& j, int& e) {
-    const int q = (int)(((double)k + 0.5) / (double)nn);
-    e = k - q * nn;
+  auto pair_of = [&](int q, int& i, int& j) {   // e+ pair index q -> (i, j > i)
     const double b = 2.0 * np - 1.0;
     int r = (int)((b - sqrt(fmax(b * b - 8.0 * q, 0.0))) * 0.5);
     r = r < 0 ? 0 : (r > np - 2 ? np - 2 : r);
@@ -1535,6 +1554,44 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     i = r;
     j = q - r * (2 * np - r - 1) / 2 + r + 1;
   };
+  auto decode = [&](int k, int& i, int& j, int& e) {
+    const int q = (int)(((double)k + 0.5) / (double)nn);
+    e = k - q * nn;
+    pair_of(q, i, j);
+  };
+  // ---- prefilter: bit p of spw for every track pair a triple can use (the
+  // e+ pairs in the order of their index q, then the e+e- pairs (i, e) at
+  // npair + i nn + e): whether its circles may meet near the target.  A
+  // triple whose three pairs do not all pass has no vertex estimate, so it
+  // is counted (and listed) but not queued for one; at lambda = 64 about
+  // four in five energy-passing triples drop out here.  Frames with more
+  // pairs than the table holds queue every energy-passing triple.
+  __shared__ unsigned long long spw[kPairWords];
+  const int npairs = npair + np * nn;
+  const bool pf = total >= kPairFilterMin && npairs <= 64 * kPairWords;
+  if (pf) {
+    const double lim = (double)C.r_target + (double)C.target_tol;
+    for (int base = 0; base < npairs; base += kWave) {
+      const int p = base + lane;
+      bool ok = false;
+      if (p < npairs) {
+        int ta, tb;
+        if (p < npair) {
+          int i, j;
+          pair_of(p, i, j);
+          ta = sid[i]; tb = sid[j];
+        } else {
+          const int i = (p - npair) / nn, e = p - npair - i * nn;
+          ta = sid[i]; tb = sid[kVtxTracks - 1 - e];
+        }
+        ok = pair_may_meet(vt[ta], vt[tb], lim * lim);
+      }
+      const unsigned long long m = ballot(ok);
+      if (lane == 0) spw[base / kWave] = m;
+    }
+    __syncthreads();
+  }
+  auto pair_bit = [&](int p) -> bool { return (spw[p >> 6] >> (p & 63)) & 1ull; };
   // ---- energy test over every triple (the count is exact even above the
   // cap), and while the count stays within the cap, the passing triples are
   // ballot-compacted into an LDS queue whose full waves get the vertex
@@ -1605,6 +1662,9 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     const unsigned long long bm = ballot(ep);
     if (bm == 0ull) continue;   // wave-uniform
     const int c = __popcll(bm);
+    // queued for the estimate: energy-passing, and all three pairs may meet
+    const bool eq = ep && (!pf || (pair_bit(i * (2 * np - i - 1) / 2 + j - i - 1) &&
+                                   pair_bit(npair + i * nn + e) && pair_bit(npair + j * nn + e)));
     if (rec.rows) {   // debug record (wave-uniform pointer)
       int r0 = 0;
       if (lane == 0) r0 = atomicAdd(rec.n, c);
@@ -1615,8 +1675,9 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     }
     cnt += c;
     if (cnt > C.max_combo) continue;   // over the cap: only counted from here on
-    if (ep) sk[nq + rank_below(bm)] = k;
-    nq += c;
+    const unsigned long long bq = ballot(eq);
+    if (eq) sk[nq + rank_below(bq)] = k;
+    nq += __popcll(bq);
     if (nq >= kWave) {
       __syncthreads();
       estimate(kWave);
@@ -1791,7 +1852,7 @@ struct RangeId {
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z, int n_hits,
                const int32_t* __restrict__ lo, Consts C, TripList T, const int32_t* __restrict__ res,
-               const int32_t* __restrict__ tslot, int nslot, const int32_t* __restrict__ counters,
+               const int32_t* __restrict__ tslot, int nslot, int32_t* __restrict__ counters,
                const int32_t* __restrict__ cand, const int32_t* __restrict__ vbase, const int32_t* __restrict__ vpos,
                int vcap, VTrack* __restrict__ vt, int32_t* __restrict__ vok, uint32_t* __restrict__ flags,
                int32_t* __restrict__ counts, float* __restrict__ vtx) {
@@ -1807,7 +1868,18 @@ k_vframes_list(const float* __restrict__ X, const float* __restrict__ Y, const f
     const int32_t h[4] = {eh.g0, eh.g1, eh.g2, eh.b3 + res[4 * e + 1]};
     return vtrack_make(X, Y, Z, n_hits, h, C, v);
   };
-  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+  // candidate frames: the first by block index, then, when there are more
+  // candidates than waves, claimed one at a time (their work varies by
+  // orders of magnitude at high rates, so a fixed deal leaves the slowest
+  // wave far behind); each wave's last claim is past the end, so every wave
+  // leaves the loop
+  auto next = [&]() {
+    if (nc <= (int)gridDim.x) return nc;
+    int v = 0;
+    if (lane == 0) v = (int)gridDim.x + atomicAdd(&counters[16], 1);
+    return lane_value(v, 0);
+  };
+  for (int c = blockIdx.x; c < nc; c = next()) {
     const int f = cand[c];
     const int nt = counts[3 * f + 1];
     if (nt <= kSmallSlots) {
