@@ -1650,14 +1650,27 @@ __device__ void vertex_wave(int f, int n, const Id& id, const VTrack* __restrict
     __syncthreads();
   };
   int cnt = 0, nq = 0;
+  // each lane's triple (ci, cj, ce) of flat index base + lane: decoded once,
+  // then advanced by kWave = stq pairs and ste e- tracks per round with
+  // integer steps (a row i of e+ pairs holds np - 1 - i of them)
+  const int stq = nn > 0 ? kWave / nn : 0, ste = kWave - stq * nn;
+  int ci = 0, cj = 0, ce = 0;
+  if (lane < total) decode(lane, ci, cj, ce);
   for (int base = 0; base < total; base += kWave) {
     const int k = base + lane;
-    int i = 0, j = 0, e = 0;
+    const int i = ci, j = cj, e = ce;
     bool ep = false;
     if (k < total) {
-      decode(k, i, j, e);
       const double s = sE[i] + sE[j] + sE[kVtxTracks - 1 - e];
       ep = s >= elo && s <= ehi;
+    }
+    if (k + kWave < total) {   // the next index exists: its pair row is reached
+      int dq = stq;
+      ce += ste;
+      if (ce >= nn) { ce -= nn; ++dq; }
+      int off = cj - ci - 1 + dq, len = np - 1 - ci;
+      while (off >= len) { off -= len; ++ci; --len; }
+      cj = ci + 1 + off;
     }
     const unsigned long long bm = ballot(ep);
     if (bm == 0ull) continue;   // wave-uniform
