@@ -96,17 +96,26 @@ struct Cursor {
   int id, used;
 };
 
-// Wave w < pre of the cuts starts with a chunk of its own (so that the waves
-// do not all queue on the bump counter at the start: atomics on one address
-// are serialised); its row is written here.  The ids go XCD-major (the waves
-// of one XCD, w mod 8, own consecutive chunks): consecutive slices of the
-// track stage, which run at the same time on different XCDs, then read
-// frames eight apart rather than neighbouring frames, whose hits share cache
-// lines (the fits run 10 % faster so).
-__device__ inline Cursor cursor_start(const TripList& T, int w) {
-  if (w >= T.pre) return Cursor{kNoChunk, 0};
-  const int q = T.pre / 8;
-  const int id = w < 8 * q ? (w % 8) * q + w / 8 : w;
+// Logical index of block b of G: XCD-major.  Blocks are dealt to the eight
+// XCDs in turn (b mod 8), so this gives the blocks of one XCD consecutive
+// indices; with frames dealt cyclically by logical index (g, g + G, ...) the
+// frames one XCD works on at a time are neighbours, whose hit segments share
+// cache lines in that XCD's L2 instead of being fetched into several.
+__device__ inline int xcd_major(int b, int G) {
+  const int q = G / 8;
+  return b < 8 * q ? (b % 8) * q + b / 8 : b;
+}
+
+// The wave of logical index g < pre (the index its frames are dealt by)
+// starts with a chunk of its own (so that the waves do not all queue on the
+// bump counter at the start: atomics on one address are serialised); its
+// row is written here.  The ids go XCD-major over g: consecutive chunks, the
+// slices of the track stage that run at the same time on different XCDs,
+// then hold frames eight apart rather than neighbouring frames, whose hits
+// share cache lines (the fits run 10 % faster so).
+__device__ inline Cursor cursor_start(const TripList& T, int g) {
+  if (g >= T.pre) return Cursor{kNoChunk, 0};
+  const int id = xcd_major(g, T.pre);
   if (threadIdx.x == 0) {
     int32_t* row = T.chunks + 4 * id;
     row[0] = id * T.chunk; row[1] = 0; row[2] = 0; row[3] = 0;
@@ -650,11 +659,12 @@ k_cuts(const float* __restrict__ X, const float* __restrict__ Y, const float* __
        int32_t* __restrict__ counts, float* __restrict__ vtx, int32_t* __restrict__ ccnt, TripList T,
        int32_t* __restrict__ counters, int32_t* __restrict__ claims, int32_t* __restrict__ defer) {
   __shared__ CutLds<TT> L;
-  Cursor cur = cursor_start(T, (int)blockIdx.x);
+  Cursor cur = cursor_start(T, xcd_major((int)blockIdx.x, (int)gridDim.x));
   int done = 0, selected = 0;   // nothing is fitted here
   const int G = gridDim.x;
+  const int g0 = xcd_major((int)blockIdx.x, G);
   frame_pipeline(
-      (int)blockIdx.x < F ? (int)blockIdx.x : -1, [&](int g) { return g < F - G ? g + G : -1; },
+      g0 < F ? g0 : -1, [&](int g) { return g < F - G ? g + G : -1; },
       [&](int f, const FrameRegs& R) {
         selected += cut_frame<TT>(f, R, X, Y, Z, n_hits, C, L, T, cur, done, flags, counts, vtx, ccnt, counters,
                                   defer);
@@ -1008,7 +1018,7 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
           int32_t* __restrict__ defer) {
   __shared__ CutLds<TT> L;
   const int lane = threadIdx.x;
-  Cursor cur = cursor_start(T, (int)blockIdx.x);
+  Cursor cur = cursor_start(T, xcd_major((int)blockIdx.x, (int)gridDim.x));
   int done = 0, selected = 0;
   auto fit = [&](int k) {   // fit entries [done, done + k) of the current chunk, lane j taking done + j
     const bool active = lane < k;
@@ -1064,7 +1074,8 @@ k_batched(const float* __restrict__ X, const float* __restrict__ Y, const float*
     if (g + 1 < fe) return g + 1;
     return claim_next();
   };
-  frame_pipeline((int)blockIdx.x < Fs ? (int)blockIdx.x : claim_next(), next, body, lo, X, Y, Z, n_hits);
+  const int g0 = xcd_major((int)blockIdx.x, G);
+  frame_pipeline(g0 < Fs ? g0 : claim_next(), next, body, lo, X, Y, Z, n_hits);
   if constexpr (kFuse) {
     if (cur.used > done) fit(cur.used - done);
   }
