@@ -158,11 +158,16 @@ const char *mu3e_status_string(int status);
 
 /* Workspace bytes for mu3e_select_frames over n_frames frames with room for
  * triplet_capacity (<= 2^30) selected triplets and track_capacity tracks of
- * vertex candidate frames in total.  The triplet list is shared by all waves in chunks of
- * triplet_capacity / (2 * waves) entries (clamped to [64, 4096]), so allow
- * about twice the expected number of selected triplets; a run whose lists
- * fill up reports it in counters[2] (mu3e_debug_t); its outputs are then
- * incomplete and the call should be repeated with larger capacities.
+ * vertex candidate frames in total.  The triplet list is shared by all waves
+ * of the cuts in chunks of triplet_capacity / (2 * waves) entries (clamped to
+ * [64, 4096]; waves = 20 per compute unit, or the plan's persistent waves),
+ * so allow about twice the expected number of selected triplets.  Whatever
+ * the capacities, no frame is passed on incomplete: a frame whose selected
+ * triplets did not all fit, whose undecided track could not be queued for
+ * the float64 re-evaluation, or whose tracks did not fit the vertex table is
+ * flagged MU3E_LIST_FULL | MU3E_KEEP (kept for storage, as the paper keeps
+ * an overflowing frame), and the run reports it in counters[2]
+ * (mu3e_debug_t); larger capacities only lower the number of such frames.
  * Returns 0 for invalid sizes. */
 size_t mu3e_select_workspace_size(int32_t n_frames, int32_t triplet_capacity,
                                   int32_t track_capacity);
