@@ -734,13 +734,14 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
   if (F32 && near) return -1;
   if (!reach) return 0;
   T best = (T)1e30, second = (T)1e30;
-  int ib = -1;
-  float bx = 0.f, by = 0.f, bz = 0.f;   // the nearest hit so far
+  int ib = -1;   // the nearest hit so far (its coordinates are read again after the scan)
   auto consider = [&](float x, float y, float z, int g) {
     const T dx = (T)x - px, dy = (T)y - py, dz = (T)z - pz;
     const T d2 = dx * dx + dy * dy + dz * dz;
-    if (d2 < best) { second = best; best = d2; ib = g; bx = x; by = y; bz = z; }
-    else if (d2 < second) second = d2;
+    const bool nb = d2 < best;
+    second = nb ? best : (d2 < second ? d2 : second);
+    ib = nb ? g : ib;
+    best = nb ? d2 : best;
   };
   auto quad = [&](int g) {   // hits g .. g+3, all inside [b3, b4); 16-byte loads at dword-aligned addresses
     float4 vx, vy, vz;
@@ -767,6 +768,7 @@ __device__ inline int track_eval(const float* __restrict__ X, const float* __res
       if (k < m) consider(tx[k], ty[k], tz[k], g + k);
   }
   if (ib < 0) return 0;
+  const float bx = X[ib], by = Y[ib], bz = Z[ib];
   if (F32 && second < (T)1e29) {
     const T eps = (T)1e-3;   // bound on the float32 error of the predicted point [mm]
     if (second - best <= (T)2 * eps * (m_sqrt(best) + m_sqrt(second)) + (T)1e-5 * second) return -1;
