@@ -86,7 +86,7 @@ MUTANTS = {
                          "chi2 += (dx * dx + dy * dy) / sg2[k];")],
     "psum_pz_with_sin": [("sz += t.p * std::cos(t.theta1);", "sz += t.p * std::sin(t.theta1);")],
     "energy_sum_two_tracks": [("double sE = A.E + B.E + C.E;", "double sE = A.E + B.E;")],
-    # Refined vertex (Section VII's more precise reconstruction)
+    # Refined vertex (the finer vertex fit that Section VII names as future work)
     "refine_helix_forward": [("double ps = ps0 + (t.charge > 0 ? phi : -phi);",
                               "double ps = ps0 + (t.charge > 0 ? -phi : phi);")],
     "refine_z_slope_sin": [("p[2] = t.h0[2] - phi * t.rbar * std::cos(t.theta1);",
