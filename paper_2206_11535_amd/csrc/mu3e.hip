@@ -1196,9 +1196,10 @@ __device__ inline bool vertex_points(const VTrack* T0, const VTrack* T1, const V
     const double d = sqrt(dx * dx + dy * dy);
     P.nq[k] = 0;
     if (d == 0.0 || d > A.rt + B.rt || d < fabs(A.rt - B.rt)) return false;
-    const double a = (A.rt * A.rt - B.rt * B.rt + d * d) / (2.0 * d);
+    const double id = 1.0 / d;
+    const double a = (A.rt * A.rt - B.rt * B.rt + d * d) * (0.5 * id);
     const double h = sqrt(fmax(A.rt * A.rt - a * a, 0.0));
-    const double ux = dx / d, uy = dy / d;
+    const double ux = dx * id, uy = dy * id;
     // the two intersections (s = -1, +1), kept in that order if near the target
     const double x0 = A.cx + a * ux + h * uy, y0 = A.cy + a * uy - h * ux;
     const double x1 = A.cx + a * ux - h * uy, y1 = A.cy + a * uy + h * ux;
@@ -1258,39 +1259,48 @@ __device__ inline bool vertex_combo(const VTrack* T0, const VTrack* T1, const VT
     const bool second = (c >> k) & 1;   // selects without a dynamic index (no scratch)
     const double x = second ? P.qx[k][1] : P.qx[k][0], y = second ? P.qy[k][1] : P.qy[k][0];
     const double s2 = second ? P.s2[k][1] : P.s2[k][0];
-    w += 1.0 / s2; mx += x / s2; my += y / s2;
+    const double iw = 1.0 / s2;
+    w += iw; mx += x * iw; my += y * iw;
   }
-  mx /= w; my /= w;
-  double px[3], py[3], pz[3], s2k[3];
+  const double iwt = 1.0 / w;
+  mx *= iwt; my *= iwt;
+  // per track: the point of closest approach, its turning angle, z and the
+  // inverse variance (one division each), and the unit radial direction
+  // (reused for the momentum below)
+  double px[3], py[3], pz[3], ws[3], ux[3], uy[3];
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const VTrack& t = *tk[k];
     const double ex = mx - t.cx, ey = my - t.cy;
     const double en = sqrt(ex * ex + ey * ey);
     if (en == 0.0) return false;
-    px[k] = t.cx + t.rt * ex / en;
-    py[k] = t.cy + t.rt * ey / en;
+    const double ien = 1.0 / en;
+    ux[k] = ex * ien;
+    uy[k] = ey * ien;
+    px[k] = t.cx + t.rt * ux[k];
+    py[k] = t.cy + t.rt * uy[k];
     const double dphi = back_turn(t, px[k], py[k]);
     pz[k] = t.hz - dphi * t.rbar * t.cth;
     const double s = t.rt * dphi;
-    s2k[k] = t.sms0 * t.sms0 * s * s + (double)C.sig_pix * (double)C.sig_pix;
+    ws[k] = 1.0 / (t.sms0 * t.sms0 * s * s + (double)C.sig_pix * (double)C.sig_pix);
   }
-  double wz = 0, mz = 0;
-  for (int k = 0; k < 3; ++k) { wz += 1.0 / s2k[k]; mz += pz[k] / s2k[k]; }
-  mz /= wz;
+  const double wz = ws[0] + ws[1] + ws[2];
+  const double mz = (pz[0] * ws[0] + pz[1] * ws[1] + pz[2] * ws[2]) / wz;
   double chi2 = 0;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double ex = px[k] - mx, ey = py[k] - my, ez = pz[k] - mz;
-    chi2 += (ex * ex + ey * ey + ez * ez) / s2k[k];
+    chi2 += (ex * ex + ey * ey + ez * ez) * ws[k];
   }
   const double dt = cone_dist(sqrt(mx * mx + my * my), mz, C);
   double sx = 0, sy = 0, sz = 0;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     const VTrack& t = *tk[k];
-    const double ux = (px[k] - t.cx) / t.rt, uy = (py[k] - t.cy) / t.rt;
     const double pt = kCLight * (double)C.b * t.rt;
     // travel direction: clockwise (positive) -> (uy, -ux)
-    sx += pt * t.q * uy;
-    sy -= pt * t.q * ux;
+    sx += pt * t.q * uy[k];
+    sy -= pt * t.q * ux[k];
     sz += t.p * t.cth;
   }
   const double ps = sqrt(sx * sx + sy * sy + sz * sz);
