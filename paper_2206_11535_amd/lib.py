@@ -441,11 +441,14 @@ class ChunkStream:
     and a selection bound to them (the batched plan, or the plain form), and
     its own stream.  submit() fills the next slot's pinned chunk through
     `fill(view)` (the readout writing into host memory), then queues on the
-    slot's stream: the copy to the GPU, mu3e_chunk_unpack, the selection and
-    the copy of the frame flags back; so one chunk's copies overlap another
-    chunk's selection.  A slot is reused once its previous chunk is done."""
+    slot's stream: the copy to the GPU (of the records and the tail only,
+    as the tail in host memory gives them), mu3e_chunk_unpack, the selection
+    and the copy of the frame flags back; so one chunk's copies overlap
+    another chunk's selection.  A slot is reused once its previous chunk is
+    done.  Four slots keep the copy engine busy (with three the loop ran at
+    half the rate, waiting on slots)."""
 
-    def __init__(self, params: dict, chunk_bytes: int, max_frames: int, n_buffers: int = 3, form: str = "batched",
+    def __init__(self, params: dict, chunk_bytes: int, max_frames: int, n_buffers: int = 4, form: str = "batched",
                  triplet_capacity: int | None = None, track_capacity: int | None = None, tuning: dict | None = None,
                  device="cuda"):
         import torch
@@ -488,10 +491,18 @@ class ChunkStream:
         sl = self.slots[k]
         if sl["event"] is not None:
             sl["event"].synchronize()   # the slot's previous chunk is done
-        fill(sl["host"].numpy())
+        buf = sl["host"].numpy()
+        fill(buf)
+        front, tail = self._used(buf)
         st = sl["stream"]
         with torch.cuda.stream(st):
-            sl["dchunk"].copy_(sl["host"], non_blocking=True)
+            if front is None:   # an inconsistent tail: the whole buffer, for mu3e_chunk_unpack to reject
+                sl["dchunk"].copy_(sl["host"], non_blocking=True)
+            else:               # only the records and the tail (the space between is never read)
+                nb = self.chunk_bytes
+                if front > 0:
+                    sl["dchunk"][:front].copy_(sl["host"][:front], non_blocking=True)
+                sl["dchunk"][nb - tail:].copy_(sl["host"][nb - tail:], non_blocking=True)
             h = sl["hits"]
             _check(self.L.mu3e_chunk_unpack(_ptr(sl["dchunk"]), self.chunk_bytes, self.max_frames, self.max_hits,
                                             _ptr(h.x), _ptr(h.y), _ptr(h.z), _ptr(h.layer_offsets), _ptr(sl["info"]),
@@ -506,6 +517,20 @@ class ChunkStream:
             ev.record(st)
         sl["event"] = ev
         return k
+
+    def _used(self, buf):
+        """(front, tail) bytes a filled chunk uses, read from its tail in host
+        memory: the records of offsets[4F] hits and the tail of 4F + 2 int32;
+        (None, None) if the tail does not describe a chunk of this buffer."""
+        nb = self.chunk_bytes
+        F = int(buf[nb - 4:nb].view(np.int32)[0])
+        if not 0 <= F <= self.max_frames:
+            return None, None
+        tail = 4 * (4 * F + 2)
+        n = int(buf[nb - 8:nb - 4].view(np.int32)[0])
+        if n < 0 or 12 * n + tail > nb:
+            return None, None
+        return 12 * n, tail
 
     def result(self, k: int):
         """(frames, flags[frames]) of the chunk last submitted to slot k
