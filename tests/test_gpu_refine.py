@@ -118,13 +118,13 @@ def gpu_triples(lib, fs, p):
     mu3e_vertex_debug) for a batch."""
     import torch
     dh = lib.to_device(fs)
-    sel = lib.select_frames(dh, p)
+    F = fs.n_frames
+    sel = lib.select_frames(dh, p, triplet_capacity=1024 * F + 65536, track_capacity=64 * F + 4096)
     torch.cuda.synchronize()
     _, tracks, kf, c = sel.lists(fs.layer_offsets)
     assert c[2] == 0
     order = np.lexsort((tracks[:, 3], tracks[:, 2], tracks[:, 1], tracks[:, 0]))
     tracks = tracks[order]
-    F = fs.n_frames
     off = np.searchsorted(tracks[:, 0], np.arange(F + 1)).astype(np.int32)
     th = np.ascontiguousarray(tracks[:, 1:5], dtype=np.int32)
     th_d = torch.from_numpy(th).cuda()
@@ -196,3 +196,34 @@ def test_invalid_rows_and_tracks(lib):
     e, es = lib.vertex_refine(dh, torch.from_numpy(th).cuda(), torch.zeros((0, 4), dtype=torch.int32).cuda(),
                               default_params())
     assert e.shape == (0, 8) and es.shape == (0,)
+
+
+def test_pileup_triples_and_determinism(lib):
+    """The energy-passing triples of a pile-up batch (lambda = 30, caps
+    lifted): the same comparison with the oracle on a sample of them; two
+    calls give bitwise the same outputs; a device count of 0 processes no
+    row."""
+    import torch
+    fs = synth.generate(4, n_frames=600, salt=29)
+    p = lifted_caps()
+    dh, th, th_d, rows = gpu_triples(lib, fs, p)
+    m = len(rows)
+    print(f"case: pile-up, {m} energy-passing triples of {len(th)} tracks", flush=True)
+    assert m > 20000
+    a, sa = lib.vertex_refine(dh, th_d, rows, p)
+    b, sb = lib.vertex_refine(dh, th_d, rows, p)
+    zero = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c, sc = lib.vertex_refine(dh, th_d, rows, p, n_valid=zero)
+    torch.cuda.synchronize()
+    assert torch.equal(sa, sb) and torch.equal(torch.nan_to_num(a, nan=-7.0), torch.nan_to_num(b, nan=-7.0))
+    assert (sc == -3).all() and torch.isnan(c).all()
+    r = rows.cpu().numpy()
+    st = sa.cpu().numpy()
+    # every refined row and as many others, at most 6,000 rows for the oracle
+    rng = np.random.default_rng(3)
+    pick = np.nonzero(st != 0)[0]
+    other = np.nonzero(st == 0)[0]
+    pick = np.concatenate([pick[:3000], rng.choice(other, min(len(other), 3000), replace=False)])
+    oo, ost = oracle.refine4(hits_of(fs, th[r[pick, 1:4]]), p)
+    n = compare(a[pick], sa[pick], oo, ost, "pile-up triples")
+    assert n >= 5   # signal is in 1 % of frames; background triples rarely pass the rough estimate
