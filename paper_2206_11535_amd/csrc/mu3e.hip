@@ -232,11 +232,28 @@ __device__ inline Verdict cos_test(float x0, float y0, float x1, float y1, float
   return window((a + b) * invRR, 8.0f * kU32 * (fabsf(a) + fabsf(b)) * invRR, lo, hi);
 }
 
-// Delta lambda = tan(lambda_12) - tan(lambda_01) in a closed window.
-__device__ inline Verdict dl_test(float z0, float z1, float t12, const Consts& C) {
-  const float t01 = (z1 - z0) * C.inv01;
-  const float dl = t12 - t01;
-  return window(dl, 8.0f * kU32 * (fabsf(t01) + fabsf(t12) + fabsf(dl)), C.dl_lo, C.dl_hi);
+// Delta lambda = tan(lambda_12) - tan(lambda_01) in a closed window, as a
+// window on z0: with t12 = (z2 - z1) / (R2 - R1) fixed by the (h1, h2) pair,
+// Delta lambda = t12 - (z1 - z0) / (R1 - R0) increases with z0 (R1 > R0),
+// so it lies in [lo, hi] exactly when z0 lies in
+// [z1 - (t12 - lo)(R1 - R0), z1 - (t12 - hi)(R1 - R0)].  The edges are
+// computed once per pair in float32; e bounds their rounding error (each
+// edge is within 7 u (|edge| + (R1 - R0)(|t12| + |lo|)) of the exact one,
+// u = 2^-24, from the roundings of z2 - z1, 1 / (R2 - R1), the product,
+// t12 - lo, R1 - R0 and the fused multiply-add).  Inside the inner edges
+// the combination passes with a margin far above the float64 rounding of
+// Delta lambda, outside the outer edges it fails, in between the float64
+// refinement decides.
+struct ZWindow {
+  float in_lo, in_hi, out_lo, out_hi;
+};
+
+__device__ inline ZWindow dl_window(float z1, float z2, const Consts& C) {
+  const float t12 = (z2 - z1) * C.inv12;
+  const float za = fmaf(-(t12 - C.dl_lo), C.d01, z1);
+  const float zb = fmaf(-(t12 - C.dl_hi), C.d01, z1);
+  const float e = 16.0f * kU32 * (fabsf(za) + fabsf(zb) + C.d01 * (fabsf(t12) + C.dl_abs));
+  return {za + e, zb - e, za - e, zb + e};
 }
 
 // |r_tc| in a closed window, tested as r_tc^2 = d01^2 d12^2 d20^2 / (4 cross^2)
@@ -420,39 +437,37 @@ __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, in
     const bool have = lane < k;
     const uint32_t e = have ? L.spend[lane] : 0u;
     const int i1 = e & 0xff, i2 = (e >> 8) & 0xff;
-    unsigned long long w0 = have ? L.sm01[W * i1] : 0ull;
-    unsigned long long w1 = (W == 2 && have) ? L.sm01[W * i1 + 1] : 0ull;
-    const float z1 = L.sz[TT + i1], z2 = L.sz[2 * TT + i2];
-    const float t12 = (z2 - z1) * C.inv12;
-    while (ballot((w0 | w1) != 0ull) != 0ull) {
-      // next partner, taken without a branch: the lowest set bit of the
-      // first non-empty mask word
-      const bool has = (w0 | w1) != 0ull;
-      const bool in0 = w0 != 0ull;
-      const unsigned long long w = in0 ? w0 : w1;
-      const unsigned long long rest = w & (w - 1);
-      const int i0 = has ? (in0 ? 0 : 64) + (int)__builtin_ctzll(w) : 0;
-      w0 = in0 ? rest : w0;
-      w1 = in0 ? w1 : rest;
-      const float z0 = L.sz[i0];
-      const Verdict vd = dl_test(z0, z1, t12, C);
-      // ambiguous combinations are queued too, marked; the r_tc stage
-      // decides them in float64 (rare), so the rounds carry no branch
-      const bool pass = has && (vd.pass || vd.amb);
-      const unsigned long long bm = ballot(pass);
-      if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16) | (vd.amb ? kDlAmbiguous : 0u);
-      nq += __popcll(bm);
-      if (nq >= kWave) {
-        __syncthreads();
-        test(kWave);
-        const int rem = nq - kWave;
-        const uint32_t v = lane < rem ? L.sjoin[kWave + lane] : 0u;
-        __syncthreads();
-        if (lane < rem) L.sjoin[lane] = v;
-        __syncthreads();
-        nq = rem;
+    const ZWindow zw = dl_window(L.sz[TT + i1], L.sz[2 * TT + i2], C);
+    // the partners of one mask word (layer-0 hits base .. base + 63), one
+    // per round: the lowest set bit, taken without a branch
+    auto rounds = [&](unsigned long long w, int base) {
+      while (ballot(w != 0ull) != 0ull) {
+        const bool has = w != 0ull;
+        const int i0 = base + (has ? (int)__builtin_ctzll(w) : 0);
+        w &= w - 1;
+        const float z0 = L.sz[i0];
+        // combinations in the ambiguous band are queued too, marked; the
+        // r_tc stage decides them in float64 (rare), so the rounds carry
+        // no branch
+        const bool pass = has && z0 >= zw.out_lo && z0 <= zw.out_hi;
+        const bool sure = z0 > zw.in_lo && z0 < zw.in_hi;
+        const unsigned long long bm = ballot(pass);
+        if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16) | (sure ? 0u : kDlAmbiguous);
+        nq += __popcll(bm);
+        if (nq >= kWave) {
+          __syncthreads();
+          test(kWave);
+          const int rem = nq - kWave;
+          const uint32_t v = lane < rem ? L.sjoin[kWave + lane] : 0u;
+          __syncthreads();
+          if (lane < rem) L.sjoin[lane] = v;
+          __syncthreads();
+          nq = rem;
+        }
       }
-    }
+    };
+    rounds(have ? L.sm01[W * i1] : 0ull, 0);
+    if (W == 2) rounds(have ? L.sm01[W * i1 + 1] : 0ull, 64);
   };
   // ---- Phi12 over all (i1, i2) pairs whose h1 has a layer-0 partner
   int npend = 0;
@@ -2304,6 +2319,8 @@ bool make_consts(const mu3e_params_t* p, Consts& C) {
   C.chi2_v = p->chi2_vertex_max; C.d_target = p->d_target_max; C.p_sum = p->p_sum_max;
   C.inv01 = 1.0f / (C.R[1] - C.R[0]);
   C.inv12 = 1.0f / (C.R[2] - C.R[1]);
+  C.d01 = C.R[1] - C.R[0];
+  C.dl_abs = fabsf(C.dl_lo) + fabsf(C.dl_hi);
   C.invRR01 = 1.0f / (C.R[0] * C.R[1]);
   C.invRR12 = 1.0f / (C.R[1] * C.R[2]);
   C.rtc_lo2 = C.rtc_lo * C.rtc_lo;

@@ -34,6 +34,7 @@ struct Consts {
   float de_max, r_target, target_tol, chi2_v, d_target, p_sum;
   // derived in float32
   float inv01, inv12;        // 1 / (R1 - R0), 1 / (R2 - R1)
+  float d01, dl_abs;         // R1 - R0, |dl_lo| + |dl_hi|
   float invRR01, invRR12;    // 1 / (R0 R1), 1 / (R1 R2)
   float rtc_lo2, rtc_hi2;    // squared |r_tc| edges
 };
