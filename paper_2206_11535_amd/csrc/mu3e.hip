@@ -32,6 +32,7 @@
 
 #include "mu3e.h"
 #include "mu3e_math.hpp"
+#include "mu3e_window.hpp"
 #include "mu3e_adjoint.hpp"
 
 #include <math.h>
@@ -233,27 +234,10 @@ __device__ inline Verdict cos_test(float x0, float y0, float x1, float y1, float
 }
 
 // Delta lambda = tan(lambda_12) - tan(lambda_01) in a closed window, as a
-// window on z0: with t12 = (z2 - z1) / (R2 - R1) fixed by the (h1, h2) pair,
-// Delta lambda = t12 - (z1 - z0) / (R1 - R0) increases with z0 (R1 > R0),
-// so it lies in [lo, hi] exactly when z0 lies in
-// [z1 - (t12 - lo)(R1 - R0), z1 - (t12 - hi)(R1 - R0)].  The edges are
-// computed once per pair in float32; e bounds their rounding error (each
-// edge is within 7 u (|edge| + (R1 - R0)(|t12| + |lo|)) of the exact one,
-// u = 2^-24, from the roundings of z2 - z1, 1 / (R2 - R1), the product,
-// t12 - lo, R1 - R0 and the fused multiply-add).  Inside the inner edges
-// the combination passes with a margin far above the float64 rounding of
-// Delta lambda, outside the outer edges it fails, in between the float64
-// refinement decides.
-struct ZWindow {
-  float in_lo, in_hi, out_lo, out_hi;
-};
-
+// window on z0 for the (h1, h2) pair (mu3e_window.hpp: the edges and their
+// rounding bound).
 __device__ inline ZWindow dl_window(float z1, float z2, const Consts& C) {
-  const float t12 = (z2 - z1) * C.inv12;
-  const float za = fmaf(-(t12 - C.dl_lo), C.d01, z1);
-  const float zb = fmaf(-(t12 - C.dl_hi), C.d01, z1);
-  const float e = 16.0f * kU32 * (fabsf(za) + fabsf(zb) + C.d01 * (fabsf(t12) + C.dl_abs));
-  return {za + e, zb - e, za - e, zb + e};
+  return dl_window_f(z1, z2, C.inv12, C.d01, C.dl_lo, C.dl_hi, C.dl_abs);
 }
 
 // |r_tc| in a closed window, tested as r_tc^2 = d01^2 d12^2 d20^2 / (4 cross^2)

@@ -107,3 +107,84 @@ def test_pair_index_split_with_approximate_reciprocal():
                 rr = np.nextafter(rr, np.float32(np.inf if step > 0 else -np.inf), dtype=np.float32)
             q = (pf * rr).astype(np.float32).astype(np.int32)
             assert np.array_equal(q, p // n), (n, step)
+
+
+WINDOW_PROGRAM = r"""
+#include "mu3e_window.hpp"
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+// Delta lambda as the float64 selection computes it (Section IV-A)
+static bool pass64(float z0, float z1, float z2, const float* R, float lo, float hi) {
+  const double d = ((double)z2 - (double)z1) / ((double)R[2] - (double)R[1]) -
+                   ((double)z1 - (double)z0) / ((double)R[1] - (double)R[0]);
+  return d >= (double)lo && d <= (double)hi;
+}
+int main() {
+  srand48(11);
+  long wrong = 0, wrong_tight = 0, amb = 0, n = 0;
+  double widest = 0;
+  for (int trial = 0; trial < 400; ++trial) {
+    float R[3] = {(float)(5 + 95 * drand48()), (float)(5 + 95 * drand48()), (float)(5 + 95 * drand48())};
+    if (R[0] > R[1]) { float t = R[0]; R[0] = R[1]; R[1] = t; }
+    if (R[1] > R[2]) { float t = R[1]; R[1] = R[2]; R[2] = t; }
+    if (R[0] > R[1]) { float t = R[0]; R[0] = R[1]; R[1] = t; }
+    if (!(R[0] < R[1] && R[1] < R[2])) continue;
+    const float lo = (float)(-0.5 * drand48()), hi = (float)(lo + 0.5 * drand48());
+    const float inv12 = 1.0f / (R[2] - R[1]), d01 = R[1] - R[0], dl_abs = fabsf(lo) + fabsf(hi);
+    const double scale = trial % 4 == 3 ? 1e3 : 200;   // hit z up to +-200 mm, some far larger
+    for (int k = 0; k < 5000; ++k) {
+      const float z1 = (float)(scale * (2 * drand48() - 1));
+      const float z2 = (float)(z1 + 1.5 * scale * (2 * drand48() - 1));
+      const mu3e::ZWindow w = mu3e::dl_window_f(z1, z2, inv12, d01, lo, hi, dl_abs);
+      const double za = 0.5 * ((double)w.in_lo + w.out_lo), e = 0.5 * ((double)w.in_lo - w.out_lo);
+      const double zb = 0.5 * ((double)w.in_hi + w.out_hi);
+      // the ambiguous band relative to the scale of the edge
+      const double t12 = ((double)z2 - z1) / ((double)R[2] - R[1]);
+      const double ref = fabs(za) + fabs(zb) + d01 * (fabs(t12) + dl_abs);
+      if (e / ref > widest) widest = e / ref;
+      for (int j = 0; j < 8; ++j) {
+        // z0 a fraction of a band to several bands from either edge
+        const double mult[4] = {0.05, 0.5, 2, 8};
+        const double edge = (j & 1) ? zb : za;
+        const float z0 = (float)(edge + (2 * drand48() - 1) * mult[(j >> 1) & 3] * e);
+        const bool p = pass64(z0, z1, z2, R, lo, hi);
+        const bool sure = z0 > w.in_lo && z0 < w.in_hi;
+        const bool cand = z0 >= w.out_lo && z0 <= w.out_hi;
+        wrong += (sure && !p) || (!cand && p);
+        amb += cand && !sure;
+        // the same window with a band 64 times narrower must get some wrong
+        const double et = e / 64;
+        const bool sure_t = z0 > za + et && z0 < zb - et, cand_t = z0 >= za - et && z0 <= zb + et;
+        wrong_tight += (sure_t && !p) || (!cand_t && p);
+        ++n;
+      }
+    }
+  }
+  printf("%ld %ld %ld %ld %.6e\n", n, wrong, wrong_tight, amb, widest);
+  return 0;
+}
+"""
+
+
+def test_dlambda_z0_window(tmp_path):
+    """The join tests Delta lambda as a window on z0 whose float32 edges
+    carry a bound on their rounding error (mu3e_window.hpp): on random
+    radii, windows and hit pairs, with z0 drawn at a fraction of the
+    ambiguous band to several bands from either edge, no z0 the window calls
+    a sure pass fails the float64 test and none outside its outer edges
+    passes it.  The same check with a band 64 times narrower does find wrong
+    decisions (so the bound is not vacuous: it is needed), and the band stays
+    below 64 u of its scale (so few candidates go to float64)."""
+    src = tmp_path / "w.cpp"
+    src.write_text(WINDOW_PROGRAM)
+    exe = tmp_path / "w"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-I", CSRC, "-o", str(exe), str(src),
+                           "-lm"])
+    n, wrong, wrong_tight, amb, widest = subprocess.check_output([str(exe)], text=True).split()
+    n, wrong, wrong_tight, amb = int(n), int(wrong), int(wrong_tight), int(amb)
+    assert n > 10_000_000 // 2, n
+    assert wrong == 0, wrong
+    assert wrong_tight > 0
+    assert 0.2 * n < amb < 0.8 * n          # the draws straddle the band
+    assert float(widest) < 64 * 2.0 ** -24, widest
