@@ -5,9 +5,9 @@ truth, with no formula of the oracle retyped:
 * per track (noiseless helices): the transverse circle (radius and centre
   as the generator curls the particle), momentum and energy, the Highland
   width at layer 0 with the true momentum and polar angle;
-* the backward turning angle and transverse path length from the layer-0
-  hit to points placed on the true circle by the generator's convention of
-  motion, and at the true vertex the path length from the z route
+* the backward turning angle, and the transverse arc length between the
+  layer-0 hit and points placed on the true circle by the generator's
+  convention of motion; at the true vertex, the arc length from the z route
   s = (z_0 - z_v) p_t / p_z; the position variance of eq. track-error there;
 * the double-cone distance at hand-placed points (closed forms);
 * the vertex estimate of three noiseless helices from three slightly
