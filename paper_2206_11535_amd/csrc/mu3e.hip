@@ -165,6 +165,11 @@ __device__ inline int rank_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// base + rank_below(m), the addition done by the bit counts themselves.
+__device__ inline int rank_below(unsigned long long m, int base) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, (unsigned)base));
+}
+
 // Makes the values available in registers at this point: the loads that
 // produce them are issued here, together, rather than sunk by the compiler
 // into the branches that first use them (each such load would cost the wave
@@ -401,7 +406,7 @@ __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, in
       }
       if (cur.id >= 0) {
         if (pass) {
-          const int slot = cur.id * T.chunk + cur.used + rank_below(bm);
+          const int slot = rank_below(bm, cur.id * T.chunk + cur.used);
           *reinterpret_cast<int2*>(T.trips + 2 * slot) = make_int2(f, (int32_t)pack_local(a0 + j0, a1 + j1, a2 + j2));
         }
         cur.used += c;
@@ -425,7 +430,8 @@ __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, in
     // the partners of one mask word (layer-0 hits base .. base + 63), one
     // per round: the lowest set bit, taken without a branch
     auto rounds = [&](unsigned long long w, int base) {
-      while (ballot(w != 0ull) != 0ull) {
+      unsigned long long live;   // the lanes with a partner left
+      while ((live = ballot(w != 0ull)) != 0ull) {
         const bool has = w != 0ull;
         const int i0 = base + (has ? (int)__builtin_ctzll(w) : 0);
         w &= w - 1;
@@ -435,8 +441,11 @@ __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, in
         // no branch
         const bool pass = has && z0 >= zw.out_lo && z0 <= zw.out_hi;
         const bool sure = z0 > zw.in_lo && z0 < zw.in_hi;
-        const unsigned long long bm = ballot(pass);
-        if (pass) L.sjoin[nq + rank_below(bm)] = e | ((uint32_t)i0 << 16) | (sure ? 0u : kDlAmbiguous);
+        // the ballot of pass as the AND of lane masks that are compare
+        // results already (a ballot of a combined condition costs two
+        // vector instructions more)
+        const unsigned long long bm = live & ballot(z0 >= zw.out_lo) & ballot(z0 <= zw.out_hi);
+        if (pass) L.sjoin[rank_below(bm, nq)] = (sure ? e : e | kDlAmbiguous) | ((uint32_t)i0 << 16);
         nq += __popcll(bm);
         if (nq >= kWave) {
           __syncthreads();
@@ -469,7 +478,7 @@ __device__ __attribute__((always_inline)) inline int join_tile(int f, int n1, in
                                C.c12_lo, C.c12_hi);
     const bool pass = act && (v.pass || v.amb);
     const unsigned long long bm = ballot(pass);
-    if (pass) L.spend[npend + rank_below(bm)] = (uint32_t)i1 | ((uint32_t)i2 << 8) | (v.amb ? kPhi12Ambiguous : 0u);
+    if (pass) L.spend[rank_below(bm, npend)] = (uint32_t)i1 | ((uint32_t)i2 << 8) | (v.amb ? kPhi12Ambiguous : 0u);
     npend += __popcll(bm);
     if (npend >= kWave) {
       __syncthreads();
